@@ -1,0 +1,227 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (``wcns_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg; never by the GPU product path.
+
+Arrays are numpy float64, variable-major: ``U[v, z, y, x]`` flattened, i.e.
+``U.reshape(nv, nz, ny, nx)`` for 3D, ``(nv, ny, nx)`` for 2D, ``(nv, nx)``
+for 1D.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wcns_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SYSTEMS = {"advection": 0, "euler": 1}
+BCS = {"periodic": 0, "transmissive": 1}
+WEIGHTS = {"js": 0, "z": 1, "fe": 2, "pfe": 3, "linear": 4}
+DIFFS = {"mnd6": 0, "md6": 1}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no FMA contraction) into liboracle.so."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call([
+            "g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
+            "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64 * 3), ("h", C.c_double * 3), ("adv", C.c_double * 3),
+        ("gamma", C.c_double), ("eps", C.c_double), ("xi", C.c_double),
+        ("kappa", C.c_double), ("cv", C.c_double),
+        ("system", C.c_int32), ("ndim", C.c_int32), ("bc", C.c_int32 * 3),
+        ("weights", C.c_int32), ("zpow", C.c_int32), ("diff", C.c_int32),
+        ("charproj", C.c_int32), ("pad_", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.POINTER(C.c_double)
+        D = C.POINTER(_Desc)
+        L.ora_nvars.argtypes = [D]
+        L.ora_residual.argtypes = [D, P, P]
+        L.ora_residual_jvp.argtypes = [D, P, P, P, P]
+        L.ora_cfl_dt.argtypes = [D, P, C.c_double]
+        L.ora_cfl_dt.restype = C.c_double
+        L.ora_check_state.argtypes = [D, P]
+        L.ora_rk3_step.argtypes = [D, P, C.c_double]
+        L.ora_rk3_step_jvp.argtypes = [D, P, P, C.c_double]
+        L.ora_run_steps.argtypes = [D, P, C.c_double, C.c_double, C.c_int64]
+        L.ora_run_to_time.argtypes = [D, P, C.c_double, C.c_double, C.c_int64,
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ora_interpolate.argtypes = [D, P, P, P]
+        L.ora_interpolate.restype = C.c_double
+        L.ora_interpolate_jvp.argtypes = [D, P, P, P]
+        L.ora_interpolate_jvp.restype = C.c_double
+        L.ora_fe_map.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
+        L.ora_fe_map.restype = C.c_double
+        L.ora_eigenvectors.argtypes = [C.c_int, C.c_int, C.c_double, P, P, P, P]
+        L.ora_euler_flux.argtypes = [C.c_int, C.c_int, C.c_double, P, P]
+        L.ora_midpoint_flux.argtypes = [D, C.c_int, P, P]
+        L.ora_count_residual_ops.argtypes = [D, P, C.POINTER(C.c_longlong)]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Problem:
+    """Problem descriptor of the oracle (its own; shares nothing with the
+    GPU library's descriptor)."""
+
+    def __init__(self, *, system="euler", ndim=1, n=(16,), h=None, gamma=1.4,
+                 adv=(1.0, 1.0, 1.0), bc="periodic", weights="fe", zpow=2,
+                 diff="mnd6", charproj=True, eps=1e-40, xi=1e6, kappa=0.5,
+                 cv=1e-3):
+        n = tuple(int(v) for v in n)
+        assert len(n) == ndim
+        if h is None:
+            h = tuple(1.0 / v for v in n)
+        h = tuple(float(v) for v in (h if np.ndim(h) else (h,) * ndim))
+        bcs = (bc,) * ndim if isinstance(bc, str) else tuple(bc)
+        d = _Desc()
+        for k in range(3):
+            d.n[k] = n[k] if k < ndim else 1
+            d.h[k] = h[k] if k < ndim else 1.0
+            d.adv[k] = float(adv[k]) if k < len(adv) else 0.0
+            d.bc[k] = BCS[bcs[k]] if k < ndim else 0
+        d.gamma, d.eps, d.xi, d.kappa, d.cv = gamma, eps, xi, kappa, cv
+        d.system = SYSTEMS[system]
+        d.ndim = ndim
+        d.weights = WEIGHTS[weights]
+        d.zpow = zpow
+        d.diff = DIFFS[diff]
+        d.charproj = 1 if charproj else 0
+        self.desc = d
+        self.ndim, self.n, self.h = ndim, n, h
+        self.nv = 1 if system == "advection" else ndim + 2
+        self.npts = int(np.prod(n))
+
+    @property
+    def shape(self):
+        return (self.nv,) + tuple(reversed(self.n))
+
+    def _ref(self):
+        return C.byref(self.desc)
+
+    def _u(self, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        assert U.size == self.nv * self.npts, (U.shape, self.shape)
+        return U
+
+    def residual(self, U):
+        U = self._u(U)
+        R = np.empty_like(U)
+        lib().ora_residual(self._ref(), _p(U), _p(R))
+        return R
+
+    def residual_jvp(self, U, V):
+        U = self._u(U)
+        V = self._u(V)
+        R = np.empty_like(U)
+        JV = np.empty_like(U)
+        lib().ora_residual_jvp(self._ref(), _p(U), _p(V), _p(R), _p(JV))
+        return R, JV
+
+    def cfl_dt(self, U, cfl):
+        U = self._u(U)
+        return lib().ora_cfl_dt(self._ref(), _p(U), cfl)
+
+    def check_state(self, U):
+        U = self._u(U)
+        return lib().ora_check_state(self._ref(), _p(U))
+
+    def rk3_step(self, U, dt):
+        U = self._u(U).copy()
+        bad = lib().ora_rk3_step(self._ref(), _p(U), dt)
+        return U, bad
+
+    def rk3_step_jvp(self, U, V, dt):
+        U = self._u(U).copy()
+        V = self._u(V).copy()
+        bad = lib().ora_rk3_step_jvp(self._ref(), _p(U), _p(V), dt)
+        return U, V, bad
+
+    def run_steps(self, U, nsteps, cfl=0.5, dt=0.0):
+        U = self._u(U).copy()
+        bad = lib().ora_run_steps(self._ref(), _p(U), cfl, dt, int(nsteps))
+        return U, bad
+
+    def run_to_time(self, U, t_end, cfl=0.5, max_steps=10**9):
+        U = self._u(U).copy()
+        s = C.c_int64(0)
+        t = C.c_double(0.0)
+        bad = lib().ora_run_to_time(self._ref(), _p(U), cfl, t_end, max_steps,
+                                    C.byref(s), C.byref(t))
+        return U, s.value, t.value, bad
+
+    def interpolate(self, u5):
+        u5 = np.ascontiguousarray(u5, dtype=np.float64)
+        wb = np.empty(3)
+        wo = np.empty(3)
+        v = lib().ora_interpolate(self._ref(), _p(u5), _p(wb), _p(wo))
+        return v, wb, wo
+
+    def interpolate_jvp(self, u5, du5):
+        u5 = np.ascontiguousarray(u5, dtype=np.float64)
+        du5 = np.ascontiguousarray(du5, dtype=np.float64)
+        d = C.c_double(0.0)
+        v = lib().ora_interpolate_jvp(self._ref(), _p(u5), _p(du5), C.byref(d))
+        return v, d.value
+
+    def midpoint_flux(self, nodes, d=0):
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        assert nodes.shape == (6, self.nv)
+        F = np.empty(self.nv)
+        lib().ora_midpoint_flux(self._ref(), d, _p(nodes), _p(F))
+        return F
+
+    def count_residual_ops(self, U):
+        U = self._u(U)
+        c = (C.c_longlong * 5)()
+        lib().ora_count_residual_ops(self._ref(), _p(U), c)
+        return dict(zip(("add", "mul", "div", "sqrt", "tanh"), list(c)))
+
+
+def fe_map(i, w, xi, kappa=0.5):
+    return lib().ora_fe_map(i, float(w), float(xi), float(kappa))
+
+
+def eigenvectors(nd, d, gamma, Ua, Ub):
+    Ua = np.ascontiguousarray(Ua, dtype=np.float64)
+    Ub = np.ascontiguousarray(Ub, dtype=np.float64)
+    L = np.zeros(25)
+    R = np.zeros(25)
+    lib().ora_eigenvectors(nd, d, gamma, _p(Ua), _p(Ub), _p(L), _p(R))
+    nv = nd + 2
+    return L.reshape(5, 5)[:nv, :nv], R.reshape(5, 5)[:nv, :nv]
+
+
+def euler_flux(nd, d, gamma, U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    F = np.zeros(nd + 2)
+    lib().ora_euler_flux(nd, d, gamma, _p(U), _p(F))
+    return F
