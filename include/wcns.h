@@ -1,0 +1,187 @@
+/*
+ * wcns.h -- C ABI of the MI355X (gfx950) WCNS-FE residual library.
+ *
+ * The library evaluates the semi-discrete residual L(U) = -sum_d dF_d/dx_d
+ * (eq. 2 of Liu, Min, Cai, Ma, Yan, "A filtered embedded weighted compact
+ * nonlinear scheme for hyperbolic conservation law", arXiv 2306.09760) of
+ * scalar advection or the Euler equations (eq. 31-32) on uniform 1D/2D/3D
+ * grids, and advances it with the three-stage SSP Runge-Kutta scheme.  The
+ * residual is, per direction and per midpoint: Roe-averaged characteristic
+ * projection, the fifth-order nonlinear interpolation to the midpoint
+ * (eq. 5-6) with JS (eq. 11), Z (eq. 14-15) or filtered-embedded (FE,
+ * eq. 20-21 and the coefficient table of Sec. 3.1; PFE switch of App. A)
+ * weights, a local Lax-Friedrichs midpoint flux, and the sixth-order
+ * midpoint-and-node flux difference (or eq. 3's midpoint-only difference).
+ *
+ * Conventions for every entry point
+ *  - Array arguments named U, R, Ubar, Rbar, lambda, work, *_dev are DEVICE
+ *    pointers on the current HIP device, owned by the caller (allocate them
+ *    with hipMalloc or PyTorch); the library never frees caller memory.
+ *    Arguments named *_host are host pointers read during the call only.
+ *  - States are float64, variable-major and x-fastest:
+ *    U[v*npts + x + nx*(y + ny*z)], npts = nx*ny*nz.  Euler variables are
+ *    (rho, rho*u, rho*v, rho*w, E) truncated to ndim + 2; advection has one.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls only enqueue work; none synchronises the device unless stated.
+ *  - Host-side validation failures return WCNS_EINVAL before anything is
+ *    enqueued; wcns_last_error() then describes the problem.  Device-side
+ *    problems (a non-finite value, rho <= 0 or p <= 0 after a stage) are
+ *    OR-ed into *status_dev (bit 0) and surface when the caller reads it.
+ *  - No exception or abort crosses this interface.  A plan must not be used
+ *    by two host threads at once, and two calls that share a workspace must
+ *    not overlap on the device.
+ */
+#ifndef WCNS_H
+#define WCNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WCNS_OK = 0,
+  WCNS_EINVAL = -1,       /* invalid argument (checked on the host)        */
+  WCNS_ENOMEM = -2,       /* host or device allocation failed               */
+  WCNS_EDEVICE = -3,      /* a HIP runtime call failed                      */
+  WCNS_ENONPHYS = -4,     /* value of a status word with bit 0 set          */
+  WCNS_EUNSUPPORTED = -5  /* valid but not implemented combination          */
+} wcns_status;
+
+typedef enum { WCNS_SYS_ADVECTION = 0, WCNS_SYS_EULER = 1 } wcns_system;
+typedef enum { WCNS_BC_PERIODIC = 0, WCNS_BC_TRANSMISSIVE = 1 } wcns_bc;
+/* JS: eq. 11.  Z: eq. 14-15.  FE: eq. 20-21 applied to the Z weights, then
+   renormalised.  PFE: App. A (FE only outside the |w_k - d_k| <= cv band).
+   LINEAR: the ideal weights d = (1/16, 10/16, 5/16) of Sec. 2. */
+typedef enum {
+  WCNS_W_JS = 0, WCNS_W_Z = 1, WCNS_W_FE = 2, WCNS_W_PFE = 3, WCNS_W_LINEAR = 4
+} wcns_weights;
+/* MND6: (3/2, -3/10, 1/30) midpoint-and-node difference (WCNS-MND, Sec. 1).
+   MD6: eq. 3, midpoint-only (75/64, -25/384, 3/640). */
+typedef enum { WCNS_DIFF_MND6 = 0, WCNS_DIFF_MD6 = 1 } wcns_diff;
+
+typedef struct wcns_desc {
+  int32_t struct_size;   /* = sizeof(wcns_desc)                                */
+  int32_t system;        /* wcns_system                                        */
+  int32_t ndim;          /* 1, 2 or 3                                          */
+  int32_t weights;       /* wcns_weights                                       */
+  int64_t n[3];          /* nodes per axis; axes >= ndim must be 1; each used
+                            axis needs n >= 9                                  */
+  double h[3];           /* grid spacing per used axis, > 0                    */
+  double adv_speed[3];   /* advection speed per axis (advection only)          */
+  int32_t bc[3];         /* wcns_bc per used axis (same at both ends)          */
+  int32_t diff;          /* wcns_diff                                          */
+  double gamma;          /* ratio of specific heats, > 1 (Euler)               */
+  double eps;            /* epsilon of eq. 11 / eq. 14 (paper: 1e-40), >= 0    */
+  double xi;             /* steepness of eq. 20 (paper: 100; 1e6 in Sec. 3.2)  */
+  double kappa;          /* null-point parameter of eq. 20 (paper: 0.5)        */
+  double cv;             /* PFE switch value of App. A (paper: 1e-3)           */
+  int32_t z_power;       /* exponent p of eq. 14, 1..4 (paper leaves it open)  */
+  int32_t char_proj;     /* 1: characteristic projection, 0: component-wise    */
+} wcns_desc;
+
+typedef struct wcns_plan wcns_plan;
+typedef struct wcns_batch_plan wcns_batch_plan;
+
+/* Fills *d with the defaults: Euler, 1D, FE weights, MND6, eps = 1e-40,
+   xi = 100, kappa = 0.5, cv = 1e-3, p = 2, gamma = 1.4, characteristic
+   projection on, periodic.  n and h must still be set. */
+void wcns_desc_init(wcns_desc* d);
+
+/* Validates *desc and creates a plan on the current device.  Allocates no
+   device memory and does not synchronise.  Errors: WCNS_EINVAL. */
+wcns_status wcns_plan_create(const wcns_desc* desc, wcns_plan** plan);
+wcns_status wcns_plan_destroy(wcns_plan* plan);
+
+/* Number of float64 values in one state: nv * nx * ny * nz. */
+int64_t wcns_state_elems(const wcns_plan* plan);
+/* Bytes of device workspace `work` that the calls below need (the caller
+   allocates it; 256-byte aligned). */
+size_t wcns_workspace_bytes(const wcns_plan* plan);
+
+/* R = L(U): one residual evaluation (all directions).  U and R must not
+   overlap.  Uses `work`.  Graph-capturable. */
+wcns_status wcns_residual(wcns_plan* plan, const double* U, double* R, void* work,
+                          void* stream);
+
+/* *dt_dev = cfl / max_i sum_d (|u_d| + c) / h_d over U (for advection
+   sum_d |a_d| / h_d).  Two deterministic kernels (block maxima, then one
+   block).  Graph-capturable. */
+wcns_status wcns_cfl_dt(wcns_plan* plan, const double* U, double cfl, double* dt_dev,
+                        void* work, void* stream);
+
+/* One SSP-RK3 step in place: U <- U^{n+1}.  If dt_dev is NULL the step is
+   cfl-limited (computed on the device from U^n and left in the workspace);
+   otherwise *dt_dev is used.  status_dev may be NULL; otherwise bit 0 is
+   OR-ed in when a stage produced a non-finite value or rho <= 0 or p <= 0.
+   No host synchronisation: graph-capturable. */
+wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev,
+                          double cfl, int32_t* status_dev, void* stream);
+
+/* Ubar += (dL/dU)^T Rbar at state U: the exact vector-Jacobian product of
+   the residual, including the weights, the FE mapping, the Roe-averaged
+   projection and the flux (conventions at non-smooth points: d|x|/dx = 0
+   at 0, a tie in max goes to the first argument).  Deterministic
+   (gather form, no atomics).  Uses `work`. */
+wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double* Rbar,
+                                  double* Ubar, void* work, void* stream);
+
+/* Reverse of one SSP-RK3 step at fixed *dt_dev: recomputes the two stage
+   states from Un and replaces lambda (in: adjoint of U^{n+1}) by the
+   adjoint of U^n.  Uses `work`. */
+wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lambda,
+                                  void* work, const double* dt_dev, void* stream);
+
+/* Measures the candidate tile shapes of this plan's kernels on U (timed with
+   HIP events; synchronises the stream) and keeps the fastest in the plan and
+   in a per-process cache keyed by shape.  U is not modified. */
+wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, void* stream);
+/* Current tile shapes: [0] x-sweep midpoints per tile, [1] y/z-sweep segment
+   length, [2] y/z-sweep lanes per workgroup. */
+void wcns_plan_get_tiles(const wcns_plan* plan, int32_t tiles[3]);
+/* Sets tile shapes (validated; WCNS_EINVAL if not among the candidates). */
+wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]);
+
+/* ----- ragged batch of independent 1D problems (one persistent launch per
+   stage; one graph-captured step) --------------------------------------- */
+/* proto: a 1D descriptor (its n[0] and h[0] are ignored).  Problem p holds
+   offsets_host[p+1] - offsets_host[p] >= 9 nodes at columns
+   offsets_host[p] .. offsets_host[p+1]-1 of every variable of the batch
+   state U[v*total + column], total = offsets_host[nprob]; its spacing is
+   h_host[p].  The library copies offsets and h (synchronously). */
+wcns_status wcns_batch_plan_create(const wcns_desc* proto, int64_t nprob,
+                                   const int64_t* offsets_host, const double* h_host,
+                                   wcns_batch_plan** plan);
+wcns_status wcns_batch_plan_destroy(wcns_batch_plan* plan);
+int64_t wcns_batch_state_elems(const wcns_batch_plan* plan);
+size_t wcns_batch_workspace_bytes(const wcns_batch_plan* plan);
+
+/* R = L(U) of every problem (per-problem spacing and boundaries). */
+wcns_status wcns_batch_residual(wcns_batch_plan* plan, const double* U, double* R,
+                                void* work, void* stream);
+
+/* One SSP-RK3 step of every problem whose time t_dev[p] < t_end, each with
+   its own dt_p = min(cfl-limited step, t_end - t_dev[p]); t_dev[p] += dt_p.
+   Finished problems are left untouched.  status_dev as in wcns_rk3_step.
+   With wcns_batch_set_graph(plan, 1) the step's kernels are captured into
+   a HIP graph on first use (for the given pointers and scalars) and
+   replayed afterwards. */
+wcns_status wcns_batch_rk3_step(wcns_batch_plan* plan, double* U, void* work, double* t_dev,
+                                double t_end, double cfl, int32_t* status_dev, void* stream);
+wcns_status wcns_batch_set_graph(wcns_batch_plan* plan, int32_t enable);
+/* Candidate midpoints-per-tile are timed on U as in wcns_plan_autotune. */
+wcns_status wcns_batch_autotune(wcns_batch_plan* plan, const double* U, void* work,
+                                void* stream);
+int32_t wcns_batch_get_tile(const wcns_batch_plan* plan);
+wcns_status wcns_batch_set_tile(wcns_batch_plan* plan, int32_t tile);
+
+const char* wcns_status_string(wcns_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* wcns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCNS_H */

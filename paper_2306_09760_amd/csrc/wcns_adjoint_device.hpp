@@ -1,0 +1,458 @@
+// Reverse-mode (vector-Jacobian) versions of the device arithmetic in
+// wcns_device.hpp, written by hand.  Each *_vjp recomputes the forward
+// intermediates it needs and propagates a cotangent backwards through them.
+// Conventions at non-smooth points: d|x|/dx = 0 at x = 0; the tie in
+// max(a, b) goes to the first argument; the PFE switch differentiates the
+// branch it takes.
+#pragma once
+
+#include "wcns_device.hpp"
+
+namespace wcns {
+
+// d tanh_sat(x) / dx = 1 - tanh^2 (exactly 0 where tanh_sat saturates).
+__device__ __forceinline__ double dtanh_from(double t) { return 1.0 - t * t; }
+
+// g_i(w) and g_i'(w) of eq. 20 (see fe_g0 .. fe_g2).
+__device__ __forceinline__ double fe_g_d(int i, double w, const InterpParams& P, double* dg) {
+  // amplitude A_j(w) = cA_j + sA_j * w (sA_j in {-1/2, 0, +1/2})
+  double g = w, d = 1.0;
+  auto term = [&](double cA, double sA, double nu) {
+    const double t = tanh_sat(P.xi * (w - nu));
+    const double A = cA + sA * w;
+    g += A * t;
+    d += sA * t + A * P.xi * dtanh_from(t);
+  };
+  if (i == 0) {
+    term(0.5 * D0, -0.5, P.nu[0]);
+    term(0.5 * (1.0 / 6.0 - D0), 0.0, P.nu[1]);
+    term(-0.5 / 6.0, 0.5, P.nu[2]);
+  } else if (i == 1) {
+    term(0.5 * D1, -0.5, P.nu[3]);
+    term(0.5 * (0.5 - D1), 0.0, P.nu[4]);
+    term(0.5 * (5.0 / 6.0 - 0.5), 0.0, P.nu[5]);
+    term(-0.5 * 5.0 / 6.0, 0.5, P.nu[6]);
+  } else {
+    term(0.5 * D2, -0.5, P.nu[7]);
+    term(0.5 * (0.5 - D2), 0.0, P.nu[8]);
+    term(-0.25, 0.5, P.nu[9]);
+  }
+  *dg = d;
+  return g;
+}
+
+// Cotangent of interp5's inputs (a, b, c, e, f) for output cotangent yb;
+// accumulates into the five references.
+__device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, double b, double c,
+                                            double e, double f, double yb, double& ab, double& bb,
+                                            double& cb, double& eb, double& fb) {
+  const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
+  const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
+  const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
+  double w0, w1, w2;
+  double c0b, c1b, c2b;
+  if (P.weights == WLIN) {
+    c0b = D0 * yb;
+    c1b = D1 * yb;
+    c2b = D2 * yb;
+  } else {
+    const double f0 = 0.5 * (a - 4.0 * b + 3.0 * c), s0 = a - 2.0 * b + c;
+    const double f1 = 0.5 * (e - b), s1 = b - 2.0 * c + e;
+    const double f2 = 0.5 * (-3.0 * c + 4.0 * e - f), s2 = c - 2.0 * e + f;
+    const double IS0 = f0 * f0 + s0 * s0;
+    const double IS1 = f1 * f1 + s1 * s1;
+    const double IS2 = f2 * f2 + s2 * s2;
+    const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
+    double a0, a1, a2, tau = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+    if (P.weights == WJS) {
+      a0 = D0 * r0 * r0;
+      a1 = D1 * r1 * r1;
+      a2 = D2 * r2 * r2;
+    } else {
+      tau = __builtin_fabs(IS0 - IS2);
+      q0 = tau * r0;
+      q1 = tau * r1;
+      q2 = tau * r2;
+      double p0 = q0, p1 = q1, p2 = q2;
+      for (int k = 1; k < P.zpow; ++k) {
+        p0 *= q0;
+        p1 *= q1;
+        p2 *= q2;
+      }
+      a0 = D0 * (1.0 + p0);
+      a1 = D1 * (1.0 + p1);
+      a2 = D2 * (1.0 + p2);
+    }
+    const double inv = rcp(a0 + a1 + a2);
+    const double z0 = a0 * inv, z1 = a1 * inv, z2 = a2 * inv;
+    bool map = (P.weights == WFE);
+    if (P.weights == WPFE) {
+      const bool inside = __builtin_fabs(z0 - D0) <= P.cv && __builtin_fabs(z1 - D1) <= P.cv &&
+                          __builtin_fabs(z2 - D2) <= P.cv;
+      map = !inside;
+    }
+    double zb0, zb1, zb2;
+    if (map) {
+      double d0, d1, d2;
+      const double g0 = fe_g_d(0, z0, P, &d0);
+      const double g1 = fe_g_d(1, z1, P, &d1);
+      const double g2 = fe_g_d(2, z2, P, &d2);
+      const double ginv = rcp(g0 + g1 + g2);
+      w0 = g0 * ginv;
+      w1 = g1 * ginv;
+      w2 = g2 * ginv;
+      const double wb0 = yb * c0, wb1 = yb * c1, wb2 = yb * c2;
+      const double sdot = wb0 * w0 + wb1 * w1 + wb2 * w2;
+      zb0 = (wb0 - sdot) * ginv * d0;
+      zb1 = (wb1 - sdot) * ginv * d1;
+      zb2 = (wb2 - sdot) * ginv * d2;
+    } else {
+      w0 = z0;
+      w1 = z1;
+      w2 = z2;
+      zb0 = yb * c0;
+      zb1 = yb * c1;
+      zb2 = yb * c2;
+    }
+    c0b = w0 * yb;
+    c1b = w1 * yb;
+    c2b = w2 * yb;
+    // z = alpha / sum(alpha)
+    const double zdot = zb0 * z0 + zb1 * z1 + zb2 * z2;
+    const double ab0 = (zb0 - zdot) * inv, ab1 = (zb1 - zdot) * inv, ab2 = (zb2 - zdot) * inv;
+    double ISb0, ISb1, ISb2;
+    if (P.weights == WJS) {
+      // alpha = d r^2, r = 1/(IS + eps): d alpha / d IS = -2 d r^3
+      ISb0 = -2.0 * D0 * r0 * r0 * r0 * ab0;
+      ISb1 = -2.0 * D1 * r1 * r1 * r1 * ab1;
+      ISb2 = -2.0 * D2 * r2 * r2 * r2 * ab2;
+    } else {
+      // alpha = d (1 + q^p), q = tau r
+      double dp0 = 1.0, dp1 = 1.0, dp2 = 1.0;  // d q^p / dq = p q^(p-1)
+      for (int k = 1; k < P.zpow; ++k) {
+        dp0 *= q0;
+        dp1 *= q1;
+        dp2 *= q2;
+      }
+      const double qb0 = D0 * ab0 * P.zpow * dp0;
+      const double qb1 = D1 * ab1 * P.zpow * dp1;
+      const double qb2 = D2 * ab2 * P.zpow * dp2;
+      const double taub = qb0 * r0 + qb1 * r1 + qb2 * r2;
+      ISb0 = -qb0 * tau * r0 * r0;
+      ISb1 = -qb1 * tau * r1 * r1;
+      ISb2 = -qb2 * tau * r2 * r2;
+      const double dd = IS0 - IS2;
+      const double sg = dd > 0.0 ? 1.0 : (dd < 0.0 ? -1.0 : 0.0);
+      ISb0 += taub * sg;
+      ISb2 -= taub * sg;
+    }
+    const double f0b = 2.0 * f0 * ISb0, s0b = 2.0 * s0 * ISb0;
+    const double f1b = 2.0 * f1 * ISb1, s1b = 2.0 * s1 * ISb1;
+    const double f2b = 2.0 * f2 * ISb2, s2b = 2.0 * s2 * ISb2;
+    ab += 0.5 * f0b + s0b;
+    bb += -2.0 * f0b - 2.0 * s0b - 0.5 * f1b + s1b;
+    cb += 1.5 * f0b + s0b - 2.0 * s1b - 1.5 * f2b + s2b;
+    eb += 0.5 * f1b + s1b + 2.0 * f2b - 2.0 * s2b;
+    fb += -0.5 * f2b + s2b;
+  }
+  ab += 0.375 * c0b;
+  bb += -1.25 * c0b - 0.125 * c1b;
+  cb += 1.875 * c0b + 0.75 * c1b + 0.375 * c2b;
+  eb += 0.375 * c1b + 0.75 * c2b;
+  fb += -0.125 * c2b;
+}
+
+// Ub += (dF/dU)^T Fb + (d lam/dU)^T lamb for the Euler flux along DIR and the
+// wave speed lam = |u_n| + c of one state.
+template <int ND, int DIR>
+__device__ __forceinline__ void flux_speed_vjp(const double* U, double gamma, const double* Fb,
+                                               double lamb, double* Ub) {
+  const double rho = U[0], E = U[ND + 1];
+  const double ir = rcp(rho);
+  double vel[ND], msq = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    vel[k] = U[1 + k] * ir;
+    msq += U[1 + k] * U[1 + k];
+  }
+  const double mm = msq * ir;
+  const double p = (gamma - 1.0) * (E - 0.5 * mm);
+  const double vn = vel[DIR];
+  double mb[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) mb[k] = 0.0;
+  double vnb = 0.0, pb = 0.0, Eb = 0.0, irb = 0.0;
+  mb[DIR] += Fb[0];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    mb[k] += Fb[1 + k] * vn;
+    vnb += Fb[1 + k] * U[1 + k];
+  }
+  pb += Fb[1 + DIR];
+  Eb += Fb[ND + 1] * vn;
+  pb += Fb[ND + 1] * vn;
+  vnb += Fb[ND + 1] * (E + p);
+  if (lamb != 0.0) {
+    vnb += lamb * (vn > 0.0 ? 1.0 : (vn < 0.0 ? -1.0 : 0.0));
+    const double X = gamma * p * ir;
+    const double cs = __builtin_sqrt(X);
+    const double Xb = lamb * 0.5 / cs;
+    pb += Xb * gamma * ir;
+    irb += Xb * gamma * p;
+  }
+  // p = (gamma-1)(E - mm/2), mm = |m|^2 ir
+  Eb += (gamma - 1.0) * pb;
+  const double mmb = -0.5 * (gamma - 1.0) * pb;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) mb[k] += mmb * 2.0 * vel[k];
+  irb += mmb * msq;
+  // vn = m_n ir
+  mb[DIR] += vnb * ir;
+  irb += vnb * U[1 + DIR];
+  Ub[0] += -irb * ir * ir;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) Ub[1 + k] += mb[k];
+  Ub[ND + 1] += Eb;
+}
+
+// Cotangent of the Roe-averaged quantities.
+template <int ND>
+struct RoeBar {
+  double vel[ND];
+  double H, c, ic, q2h, b1, b2;
+};
+
+// Propagates rb back to the two node states (accumulating into UbA, UbB).
+template <int ND>
+__device__ __forceinline__ void roe_vjp(const double* UA, const double* UB, double gamma,
+                                        const RoeState<ND>& r, RoeBar<ND> rb, double* UbA,
+                                        double* UbB) {
+  // b2 = q2h b1 ; b1 = (g-1) ic^2 ; ic = 1/c
+  rb.q2h += rb.b2 * r.b1;
+  rb.b1 += rb.b2 * r.q2h;
+  rb.ic += rb.b1 * 2.0 * (gamma - 1.0) * r.ic;
+  rb.c += -rb.ic * r.ic * r.ic;
+  // c = sqrt((g-1)(H - q2h))
+  const double Yb = rb.c * 0.5 * r.ic;
+  rb.H += Yb * (gamma - 1.0);
+  rb.q2h -= Yb * (gamma - 1.0);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) rb.vel[k] += rb.q2h * r.vel[k];
+  // Forward pieces of the average.
+  const Prim<ND> A = primitives<ND>(UA, gamma);
+  const Prim<ND> B = primitives<ND>(UB, gamma);
+  const double sA = __builtin_sqrt(UA[0]), sB = __builtin_sqrt(UB[0]);
+  const double den = rcp(sA + sB);
+  const double wA = sA * den, wB = sB * den;
+  const double HA = (UA[ND + 1] + A.p) * A.ir;
+  const double HB = (UB[ND + 1] + B.p) * B.ir;
+  double wAb = rb.H * HA, wBb = rb.H * HB;
+  const double HAb = rb.H * wA, HBb = rb.H * wB;
+  double velAb[ND], velBb[ND];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    wAb += rb.vel[k] * A.vel[k];
+    wBb += rb.vel[k] * B.vel[k];
+    velAb[k] = rb.vel[k] * wA;
+    velBb[k] = rb.vel[k] * wB;
+  }
+  const double denb = wAb * sA + wBb * sB;
+  const double Sb = -denb * den * den;
+  const double sAb = wAb * den + Sb;
+  const double sBb = wBb * den + Sb;
+  // Node A: H = (E + p) ir, vel = m ir, p = (g-1)(E - |m|^2 ir / 2), ir = 1/rho, s = sqrt(rho)
+  auto node = [&](const double* U, const Prim<ND>& Q, double s, double sb, double Hb,
+                  const double* velb, double* Ub) {
+    double irb = Hb * (U[ND + 1] + Q.p);
+    double Eb = Hb * Q.ir;
+    const double pb = Hb * Q.ir;
+    Eb += (gamma - 1.0) * pb;
+    const double mmb = -0.5 * (gamma - 1.0) * pb;
+    double msq = 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) msq += U[1 + k] * U[1 + k];
+    irb += mmb * msq;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+      Ub[1 + k] += mmb * 2.0 * Q.vel[k] + velb[k] * Q.ir;
+      irb += velb[k] * U[1 + k];
+    }
+    Ub[ND + 1] += Eb;
+    Ub[0] += -irb * Q.ir * Q.ir + sb * 0.5 / s;
+  };
+  node(UA, A, sA, sAb, HAb, velAb, UbA);
+  node(UB, B, sB, sBb, HBb, velBb, UbB);
+}
+
+// VJP of the midpoint flux: given Fb (NV), accumulate sb[0..5][NV] (must be
+// zeroed by the caller) = (dF/ds)^T Fb.
+template <int NV, int DIR>
+__device__ __forceinline__ void midpoint_flux_vjp(const InterpParams& IP, const PhysParams& PP,
+                                                  const double (&s)[6][NV], const double (&Fb)[NV],
+                                                  double (&sb)[6][NV]) {
+  if constexpr (NV == 1) {
+    const double ubL = 0.5 * (PP.adv + __builtin_fabs(PP.adv)) * Fb[0];
+    const double ubR = 0.5 * (PP.adv - __builtin_fabs(PP.adv)) * Fb[0];
+    interp5_vjp(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], ubL, sb[0][0], sb[1][0], sb[2][0],
+                sb[3][0], sb[4][0]);
+    interp5_vjp(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0], ubR, sb[5][0], sb[4][0], sb[3][0],
+                sb[2][0], sb[1][0]);
+  } else {
+    constexpr int ND = NV - 2;
+    const double gamma = PP.gamma;
+    double UL[NV], UR[NV], WL[NV], WR[NV];
+    RoeState<ND> r;
+    if (PP.charproj) {
+      r = roe_average<ND>(s[2], s[3], gamma);
+      double W[6][NV];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) project<ND, DIR>(r, s[j], W[j]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        WL[v] = interp5(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
+        WR[v] = interp5(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
+      }
+      unproject<ND, DIR>(r, WL, UL);
+      unproject<ND, DIR>(r, WR, UR);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UL[v] = interp5(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
+        UR[v] = interp5(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
+      }
+    }
+    // LLF
+    double ULb[NV], URb[NV];
+    {
+      const Prim<ND> L = primitives<ND>(UL, gamma);
+      const Prim<ND> R = primitives<ND>(UR, gamma);
+      const double lamL = __builtin_fabs(L.vel[DIR]) + __builtin_sqrt(gamma * L.p * L.ir);
+      const double lamR = __builtin_fabs(R.vel[DIR]) + __builtin_sqrt(gamma * R.p * R.ir);
+      const bool takeL = lamL >= lamR;
+      const double alpha = takeL ? lamL : lamR;
+      double alphab = 0.0, Fh[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        alphab += -0.5 * (UR[v] - UL[v]) * Fb[v];
+        ULb[v] = 0.5 * alpha * Fb[v];
+        URb[v] = -0.5 * alpha * Fb[v];
+        Fh[v] = 0.5 * Fb[v];
+      }
+      flux_speed_vjp<ND, DIR>(UL, gamma, Fh, takeL ? alphab : 0.0, ULb);
+      flux_speed_vjp<ND, DIR>(UR, gamma, Fh, takeL ? 0.0 : alphab, URb);
+    }
+    if (!PP.charproj) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        interp5_vjp(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ULb[v], sb[0][v], sb[1][v],
+                    sb[2][v], sb[3][v], sb[4][v]);
+        interp5_vjp(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v], URb[v], sb[5][v], sb[4][v],
+                    sb[3][v], sb[2][v], sb[1][v]);
+      }
+      return;
+    }
+    RoeBar<ND> rb;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) rb.vel[k] = 0.0;
+    rb.H = rb.c = rb.ic = rb.q2h = rb.b1 = rb.b2 = 0.0;
+    // Back-projection U = R W for both sides.
+    double WLb[NV], WRb[NV];
+    auto unproj_vjp = [&](const double* W, const double* Ub, double* Wb) {
+      const double sum = W[0] + W[1] + W[ND + 1];
+      const double dif = W[ND + 1] - W[0];
+      double sumb = Ub[0], difb = 0.0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Wb[v] = 0.0;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) {
+        rb.vel[k] += Ub[1 + k] * sum;
+        sumb += Ub[1 + k] * r.vel[k];
+      }
+      rb.c += Ub[1 + DIR] * dif;
+      difb += Ub[1 + DIR] * r.c;
+      const double Eb = Ub[ND + 1];
+      rb.H += Eb * (W[0] + W[ND + 1]);
+      Wb[0] += Eb * r.H;
+      Wb[ND + 1] += Eb * r.H;
+      rb.vel[DIR] += Eb * r.c * dif;
+      rb.c += Eb * r.vel[DIR] * dif;
+      difb += Eb * r.vel[DIR] * r.c;
+      rb.q2h += Eb * W[1];
+      Wb[1] += Eb * r.q2h;
+#pragma unroll
+      for (int t = 0; t < ND - 1; ++t) {
+        const int ax = tangential_axis<ND, DIR>(t);
+        Wb[2 + t] += Ub[1 + ax] + Eb * r.vel[ax];
+        rb.vel[ax] += Eb * W[2 + t];
+      }
+      Wb[0] += sumb - difb;
+      Wb[1] += sumb;
+      Wb[ND + 1] += sumb + difb;
+    };
+    unproj_vjp(WL, ULb, WLb);
+    unproj_vjp(WR, URb, WRb);
+    // Interpolation: cotangents of the projected stencil values.
+    double Wst[6][NV], Wb[6][NV];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      project<ND, DIR>(r, s[j], Wst[j]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Wb[j][v] = 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      interp5_vjp(IP, Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v], WLb[v], Wb[0][v],
+                  Wb[1][v], Wb[2][v], Wb[3][v], Wb[4][v]);
+      interp5_vjp(IP, Wst[5][v], Wst[4][v], Wst[3][v], Wst[2][v], Wst[1][v], WRb[v], Wb[5][v],
+                  Wb[4][v], Wb[3][v], Wb[2][v], Wb[1][v]);
+    }
+    // Projection W_j = L U_j.
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const double* U = s[j];
+      double um = 0.0;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) um += r.vel[k] * U[1 + k];
+      const double thb = 0.5 * Wb[j][0] - Wb[j][1] + 0.5 * Wb[j][ND + 1];
+      const double anb = 0.5 * Wb[j][0] - 0.5 * Wb[j][ND + 1];
+      sb[j][0] += Wb[j][1];
+#pragma unroll
+      for (int t = 0; t < ND - 1; ++t) {
+        const int ax = tangential_axis<ND, DIR>(t);
+        sb[j][1 + ax] += Wb[j][2 + t];
+        rb.vel[ax] -= Wb[j][2 + t] * U[0];
+        sb[j][0] -= Wb[j][2 + t] * r.vel[ax];
+      }
+      // an = (vel_n rho - m_n) ic
+      rb.vel[DIR] += anb * U[0] * r.ic;
+      sb[j][0] += anb * r.vel[DIR] * r.ic;
+      sb[j][1 + DIR] -= anb * r.ic;
+      rb.ic += anb * (r.vel[DIR] * U[0] - U[1 + DIR]);
+      // theta = b2 rho - b1 um + b1 E
+      rb.b2 += thb * U[0];
+      sb[j][0] += thb * r.b2;
+      rb.b1 += thb * (U[ND + 1] - um);
+      sb[j][ND + 1] += thb * r.b1;
+      const double umb = -thb * r.b1;
+#pragma unroll
+      for (int k = 0; k < ND; ++k) {
+        rb.vel[k] += umb * U[1 + k];
+        sb[j][1 + k] += umb * r.vel[k];
+      }
+    }
+    roe_vjp<ND>(s[2], s[3], gamma, r, rb, sb[2], sb[3]);
+  }
+}
+
+// Ub += (dF/dU)^T Fb for the physical flux at a node.
+template <int NV, int DIR>
+__device__ __forceinline__ void node_flux_vjp(const PhysParams& PP, const double (&U)[NV],
+                                              const double (&Fb)[NV], double (&Ub)[NV]) {
+  if constexpr (NV == 1) {
+    Ub[0] += PP.adv * Fb[0];
+  } else {
+    flux_speed_vjp<NV - 2, DIR>(U, PP.gamma, Fb, 0.0, Ub);
+  }
+}
+
+}  // namespace wcns

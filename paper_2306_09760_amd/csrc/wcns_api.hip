@@ -1,0 +1,793 @@
+// C ABI of the WCNS-FE library: plan management, host-side validation,
+// workspace layout, SSP-RK3 orchestration, the ragged batch with its
+// graph-captured step, and the tile autotuner.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+#include <algorithm>
+
+#include "../../include/wcns.h"
+#include "wcns_internal.hpp"
+
+using namespace wcns;
+
+namespace {
+
+thread_local std::string g_err;
+
+wcns_status fail(wcns_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+wcns_status fail(wcns_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+wcns_status hip_fail(hipError_t e, const char* what) {
+  return fail(WCNS_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define WCNS_HIP(call, what)                         \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+const int kTmCandidates[] = {64, 128, 256};
+const int kSegCandidates[] = {16, 32, 64};
+const int kBwCandidates[] = {64, 128, 256};
+
+bool in_list(int v, const int* l, int n) {
+  for (int i = 0; i < n; ++i)
+    if (l[i] == v) return true;
+  return false;
+}
+
+// Null points kappa*(psi_{i,j} + psi_{i,j-1}) of eq. 20 from the coefficient
+// table of Sec. 3.1.
+void fill_null_points(double kappa, double* nu) {
+  const double psi0[4] = {0.0, 1.0 / 16.0, 1.0 / 11.0, 1.0};
+  const double psi1[5] = {0.0, 10.0 / 16.0, 2.0 / 3.0, 10.0 / 11.0, 1.0};
+  const double psi2[4] = {0.0, 5.0 / 16.0, 1.0 / 3.0, 1.0};
+  int k = 0;
+  for (int j = 1; j <= 3; ++j) nu[k++] = kappa * (psi0[j] + psi0[j - 1]);
+  for (int j = 1; j <= 4; ++j) nu[k++] = kappa * (psi1[j] + psi1[j - 1]);
+  for (int j = 1; j <= 3; ++j) nu[k++] = kappa * (psi2[j] + psi2[j - 1]);
+}
+
+wcns_status validate(const wcns_desc* d, bool batch) {
+  if (!d) return fail(WCNS_EINVAL, "desc is NULL");
+  if (d->struct_size != (int32_t)sizeof(wcns_desc))
+    return fail(WCNS_EINVAL, "desc.struct_size %d != sizeof(wcns_desc) %d", d->struct_size,
+                (int)sizeof(wcns_desc));
+  if (d->system != WCNS_SYS_ADVECTION && d->system != WCNS_SYS_EULER)
+    return fail(WCNS_EINVAL, "unknown system %d", d->system);
+  if (d->ndim < 1 || d->ndim > 3) return fail(WCNS_EINVAL, "ndim %d not in 1..3", d->ndim);
+  if (batch && d->ndim != 1) return fail(WCNS_EINVAL, "a batch prototype must be 1D");
+  if (batch && d->system != WCNS_SYS_EULER)
+    return fail(WCNS_EUNSUPPORTED, "the batch supports the 1D Euler system");
+  if (d->weights < WCNS_W_JS || d->weights > WCNS_W_LINEAR)
+    return fail(WCNS_EINVAL, "unknown weights %d", d->weights);
+  if (d->diff != WCNS_DIFF_MND6 && d->diff != WCNS_DIFF_MD6)
+    return fail(WCNS_EINVAL, "unknown difference operator %d", d->diff);
+  if (d->z_power < 1 || d->z_power > 4) return fail(WCNS_EINVAL, "z_power %d not in 1..4", d->z_power);
+  if (!(d->eps >= 0.0) || !std::isfinite(d->eps)) return fail(WCNS_EINVAL, "eps must be >= 0");
+  if (!(d->xi > 0.0) || !std::isfinite(d->xi)) return fail(WCNS_EINVAL, "xi must be > 0");
+  if (!std::isfinite(d->kappa)) return fail(WCNS_EINVAL, "kappa must be finite");
+  if (!(d->cv >= 0.0)) return fail(WCNS_EINVAL, "cv must be >= 0");
+  if (d->system == WCNS_SYS_EULER && !(d->gamma > 1.0))
+    return fail(WCNS_EINVAL, "gamma must be > 1");
+  if (d->char_proj != 0 && d->char_proj != 1) return fail(WCNS_EINVAL, "char_proj must be 0 or 1");
+  for (int k = 0; k < 3; ++k) {
+    if (k < d->ndim) {
+      if (!batch && d->n[k] < 9) return fail(WCNS_EINVAL, "n[%d] = %lld < 9", k, (long long)d->n[k]);
+      if (!batch && !(d->h[k] > 0.0)) return fail(WCNS_EINVAL, "h[%d] must be > 0", k);
+      if (d->bc[k] != WCNS_BC_PERIODIC && d->bc[k] != WCNS_BC_TRANSMISSIVE)
+        return fail(WCNS_EINVAL, "unknown bc[%d] %d", k, d->bc[k]);
+      if (!std::isfinite(d->adv_speed[k])) return fail(WCNS_EINVAL, "adv_speed[%d] not finite", k);
+    } else if (!batch && d->n[k] != 1) {
+      return fail(WCNS_EINVAL, "n[%d] must be 1 for ndim %d", k, d->ndim);
+    }
+  }
+  if (!batch) {
+    const double np = (double)d->n[0] * (double)d->n[1] * (double)d->n[2];
+    if (np * (d->ndim + 2) > 4.0e9) return fail(WCNS_EINVAL, "grid too large");
+  }
+  return WCNS_OK;
+}
+
+void interp_params(const wcns_desc* d, InterpParams* ip) {
+  ip->eps = d->eps;
+  ip->xi = d->xi;
+  ip->cv = d->cv;
+  fill_null_points(d->kappa, ip->nu);
+  ip->weights = d->weights;
+  ip->zpow = d->z_power;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+struct TuneKey {
+  int ndim, nv, weights, diff, charproj;
+  int64_t n0, n1, n2;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(ndim, nv, weights, diff, charproj, n0, n1, n2) <
+           std::tie(o.ndim, o.nv, o.weights, o.diff, o.charproj, o.n0, o.n1, o.n2);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::tuple<int, int, int>> g_tune_cache;
+
+}  // namespace
+
+struct wcns_plan {
+  wcns_desc d;
+  int nv;
+  int64_t npts;
+  int tm, seg, bw;
+  InterpParams ip;
+  double ih[3];
+  int ncfl;
+  size_t off_W1, off_W2, off_R, off_partial, off_dt, off_A1, off_A2, off_A3, off_C, bytes;
+  size_t contrib_elems;
+};
+
+struct wcns_batch_plan {
+  wcns_desc d;
+  int64_t nprob, total;
+  std::vector<int64_t> h_offset;
+  std::vector<double> h_ih;
+  int64_t* d_offset = nullptr;
+  double* d_ih = nullptr;
+  int32_t* d_tile_prob = nullptr;
+  int32_t* d_tile_i0 = nullptr;
+  int32_t ntiles = 0;
+  int tm = 256;
+  int grid = 0;
+  int cus = 256;
+  InterpParams ip;
+  size_t off_W1, off_W2, off_dtp, bytes;
+  // graph-captured step
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::tuple<const void*, const void*, const void*, double, double, const void*, int> key;
+};
+
+namespace {
+
+wcns_status sweep_common(const wcns_plan* P, int d, SweepArgs* a) {
+  std::memset(a, 0, sizeof *a);
+  a->npts = P->npts;
+  for (int k = 0; k < 3; ++k) a->n[k] = P->d.n[k];
+  a->bc = P->d.bc[d];
+  a->diff = P->d.diff;
+  a->ih = P->ih[d];
+  a->ip = P->ip;
+  a->pp.gamma = P->d.gamma;
+  a->pp.adv = P->d.adv_speed[d];
+  a->pp.charproj = P->d.char_proj;
+  return WCNS_OK;
+}
+
+hipError_t run_sweep(const wcns_plan* P, int d, SweepArgs& a, int mode, hipStream_t s) {
+  if (d == 0) return launch_xsweep(P->nv, a, mode, P->tm, s);
+  return launch_march(P->nv, d, a, mode, P->seg, P->bw, s);
+}
+
+// R = L(U) into R.
+wcns_status residual_into(const wcns_plan* P, const double* U, double* R, hipStream_t s) {
+  for (int d = 0; d < P->d.ndim; ++d) {
+    SweepArgs a;
+    sweep_common(P, d, &a);
+    a.U = U;
+    a.out = R;
+    a.Rin = R;
+    WCNS_HIP(run_sweep(P, d, a, d == 0 ? MODE_RES : MODE_ACC, s), "residual sweep launch");
+  }
+  return WCNS_OK;
+}
+
+// out = ca*U0 + cb*(Uk + dt*L(Uk)).
+wcns_status stage(const wcns_plan* P, const double* Uk, const double* U0, double* out, double ca,
+                  double cb, const double* dt, double* Racc, int32_t* status, hipStream_t s) {
+  const int nd = P->d.ndim;
+  for (int d = 0; d < nd; ++d) {
+    SweepArgs a;
+    sweep_common(P, d, &a);
+    a.U = Uk;
+    const bool last = (d == nd - 1);
+    int mode;
+    if (last) {
+      mode = MODE_STAGE;
+      a.U0 = U0;
+      a.out = out;
+      a.Rin = (nd > 1) ? Racc : nullptr;
+      a.dt = dt;
+      a.status = status;
+      a.ca = ca;
+      a.cb = cb;
+    } else {
+      mode = (d == 0) ? MODE_RES : MODE_ACC;
+      a.out = Racc;
+      a.Rin = Racc;
+    }
+    WCNS_HIP(run_sweep(P, d, a, mode, s), "stage sweep launch");
+  }
+  return WCNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void wcns_desc_init(wcns_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof *d);
+  d->struct_size = sizeof(wcns_desc);
+  d->system = WCNS_SYS_EULER;
+  d->ndim = 1;
+  d->weights = WCNS_W_FE;
+  d->n[0] = d->n[1] = d->n[2] = 1;
+  d->h[0] = d->h[1] = d->h[2] = 1.0;
+  d->adv_speed[0] = d->adv_speed[1] = d->adv_speed[2] = 1.0;
+  d->bc[0] = d->bc[1] = d->bc[2] = WCNS_BC_PERIODIC;
+  d->diff = WCNS_DIFF_MND6;
+  d->gamma = 1.4;
+  d->eps = 1e-40;
+  d->xi = 100.0;
+  d->kappa = 0.5;
+  d->cv = 1e-3;
+  d->z_power = 2;
+  d->char_proj = 1;
+}
+
+wcns_status wcns_plan_create(const wcns_desc* desc, wcns_plan** plan) {
+  g_err.clear();
+  if (!plan) return fail(WCNS_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  wcns_status st = validate(desc, false);
+  if (st != WCNS_OK) return st;
+  wcns_plan* P = new (std::nothrow) wcns_plan();
+  if (!P) return fail(WCNS_ENOMEM, "host allocation failed");
+  P->d = *desc;
+  P->nv = desc->system == WCNS_SYS_ADVECTION ? 1 : desc->ndim + 2;
+  if (P->nv == 3 && desc->ndim != 1) {
+    delete P;
+    return fail(WCNS_EINVAL, "inconsistent nv");
+  }
+  P->npts = desc->n[0] * desc->n[1] * desc->n[2];
+  for (int k = 0; k < 3; ++k) P->ih[k] = k < desc->ndim ? 1.0 / desc->h[k] : 0.0;
+  interp_params(desc, &P->ip);
+  P->tm = 256;
+  P->seg = 32;
+  P->bw = 64;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    TuneKey k{desc->ndim, P->nv, desc->weights, desc->diff, desc->char_proj, desc->n[0], desc->n[1], desc->n[2]};
+    auto it = g_tune_cache.find(k);
+    if (it != g_tune_cache.end()) std::tie(P->tm, P->seg, P->bw) = it->second;
+  }
+  P->ncfl = cfl_blocks(P->npts);
+  const size_t state = sizeof(double) * P->nv * P->npts;
+  size_t contrib = 0;
+  for (int d = 0; d < desc->ndim; ++d)
+    contrib = std::max(contrib, adjoint_contrib_elems(P->nv, d, desc->n, desc->diff));
+  P->contrib_elems = contrib;
+  size_t o = 0;
+  P->off_W1 = o; o += align256(state);
+  P->off_W2 = o; o += align256(state);
+  P->off_R = o; o += align256(state);
+  P->off_A1 = o; o += align256(state);
+  P->off_A2 = o; o += align256(state);
+  P->off_A3 = o; o += align256(state);
+  P->off_C = o; o += align256(sizeof(double) * contrib);
+  P->off_partial = o; o += align256(sizeof(double) * P->ncfl);
+  P->off_dt = o; o += 256;
+  P->bytes = o;
+  *plan = P;
+  return WCNS_OK;
+}
+
+wcns_status wcns_plan_destroy(wcns_plan* plan) {
+  delete plan;
+  return WCNS_OK;
+}
+
+int64_t wcns_state_elems(const wcns_plan* plan) { return plan ? plan->nv * plan->npts : 0; }
+size_t wcns_workspace_bytes(const wcns_plan* plan) { return plan ? plan->bytes : 0; }
+
+void wcns_plan_get_tiles(const wcns_plan* plan, int32_t tiles[3]) {
+  if (!plan || !tiles) return;
+  tiles[0] = plan->tm;
+  tiles[1] = plan->seg;
+  tiles[2] = plan->bw;
+}
+
+wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]) {
+  g_err.clear();
+  if (!plan || !tiles) return fail(WCNS_EINVAL, "NULL argument");
+  if (!in_list(tiles[0], kTmCandidates, 3) || !in_list(tiles[1], kSegCandidates, 3) ||
+      !in_list(tiles[2], kBwCandidates, 3))
+    return fail(WCNS_EINVAL, "tile shape (%d, %d, %d) not among the candidates", tiles[0], tiles[1],
+                tiles[2]);
+  plan->tm = tiles[0];
+  plan->seg = tiles[1];
+  plan->bw = tiles[2];
+  return WCNS_OK;
+}
+
+wcns_status wcns_residual(wcns_plan* plan, const double* U, double* R, void* work, void* stream) {
+  g_err.clear();
+  (void)work;
+  if (!plan || !U || !R) return fail(WCNS_EINVAL, "NULL argument");
+  if (U == R) return fail(WCNS_EINVAL, "U and R must not overlap");
+  return residual_into(plan, U, R, (hipStream_t)stream);
+}
+
+wcns_status wcns_cfl_dt(wcns_plan* plan, const double* U, double cfl, double* dt_dev, void* work,
+                        void* stream) {
+  g_err.clear();
+  if (!plan || !U || !dt_dev || !work) return fail(WCNS_EINVAL, "NULL argument");
+  if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0");
+  char* w = (char*)work;
+  WCNS_HIP(launch_cfl(plan->nv, plan->d.ndim, U, plan->npts, plan->d.gamma, plan->ih,
+                      plan->d.adv_speed, cfl, (double*)(w + plan->off_partial), plan->ncfl,
+                      dt_dev, (hipStream_t)stream),
+           "cfl launch");
+  return WCNS_OK;
+}
+
+wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev, double cfl,
+                          int32_t* status_dev, void* stream) {
+  g_err.clear();
+  if (!plan || !U || !work) return fail(WCNS_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)work;
+  double* W1 = (double*)(w + plan->off_W1);
+  double* W2 = (double*)(w + plan->off_W2);
+  double* Racc = (double*)(w + plan->off_R);
+  const double* dt = dt_dev;
+  if (!dt) {
+    if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0 when dt_dev is NULL");
+    double* dtw = (double*)(w + plan->off_dt);
+    WCNS_HIP(launch_cfl(plan->nv, plan->d.ndim, U, plan->npts, plan->d.gamma, plan->ih,
+                        plan->d.adv_speed, cfl, (double*)(w + plan->off_partial), plan->ncfl, dtw, s),
+             "cfl launch");
+    dt = dtw;
+  }
+  wcns_status st;
+  if ((st = stage(plan, U, U, W1, 0.0, 1.0, dt, Racc, status_dev, s)) != WCNS_OK) return st;
+  if ((st = stage(plan, W1, U, W2, 0.75, 0.25, dt, Racc, status_dev, s)) != WCNS_OK) return st;
+  if ((st = stage(plan, W2, U, U, 1.0 / 3.0, 2.0 / 3.0, dt, Racc, status_dev, s)) != WCNS_OK) return st;
+  return WCNS_OK;
+}
+
+wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double* Rbar,
+                                  double* Ubar, void* work, void* stream) {
+  g_err.clear();
+  if (!plan || !U || !Rbar || !Ubar || !work) return fail(WCNS_EINVAL, "NULL argument");
+  if (Ubar == U || Ubar == Rbar) return fail(WCNS_EINVAL, "Ubar must not alias U or Rbar");
+  char* w = (char*)work;
+  for (int d = 0; d < plan->d.ndim; ++d) {
+    AdjArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.U = U;
+    a.Rbar = Rbar;
+    a.contrib = (double*)(w + plan->off_C);
+    a.Ubar = Ubar;
+    a.scale = 1.0;
+    a.npts = plan->npts;
+    for (int k = 0; k < 3; ++k) a.n[k] = plan->d.n[k];
+    a.bc = plan->d.bc[d];
+    a.diff = plan->d.diff;
+    a.ih = plan->ih[d];
+    a.ip = plan->ip;
+    a.pp.gamma = plan->d.gamma;
+    a.pp.adv = plan->d.adv_speed[d];
+    a.pp.charproj = plan->d.char_proj;
+    WCNS_HIP(launch_adjoint_dir(plan->nv, d, a, (hipStream_t)stream), "adjoint launch");
+  }
+  return WCNS_OK;
+}
+
+wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lambda, void* work,
+                                  const double* dt_dev, void* stream) {
+  g_err.clear();
+  if (!plan || !Un || !lambda || !work || !dt_dev) return fail(WCNS_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)work;
+  const int64_t len = plan->nv * plan->npts;
+  double* U1 = (double*)(w + plan->off_W1);
+  double* U2 = (double*)(w + plan->off_W2);
+  double* L = (double*)(w + plan->off_R);
+  double* l2 = (double*)(w + plan->off_A1);
+  double* l1 = (double*)(w + plan->off_A2);
+  double* tmp = (double*)(w + plan->off_A3);
+  wcns_status st;
+  // Recompute the stage states U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 (U1 + dt L(U1)).
+  if ((st = residual_into(plan, Un, L, s)) != WCNS_OK) return st;
+  WCNS_HIP(launch_lincomb(U1, Un, 1.0, L, 0.0, dt_dev, 1.0, len, s), "lincomb");
+  if ((st = residual_into(plan, U1, L, s)) != WCNS_OK) return st;
+  WCNS_HIP(launch_lincomb(U2, U1, 0.25, L, 0.0, dt_dev, 0.25, len, s), "lincomb");
+  WCNS_HIP(launch_axpy_state(U2, Un, 0.75, len, s), "axpy");
+  // Stage 3: U3 = 1/3 Un + 2/3 U2 + 2/3 dt L(U2), lambda = adjoint of U3.
+  //   l2 = 2/3 lambda + 2/3 dt J(U2)^T lambda
+  WCNS_HIP(launch_zero(tmp, len, s), "zero");
+  if ((st = wcns_residual_adjoint(plan, U2, lambda, tmp, work, stream)) != WCNS_OK) return st;
+  WCNS_HIP(launch_lincomb(l2, lambda, 2.0 / 3.0, tmp, 0.0, dt_dev, 2.0 / 3.0, len, s), "lincomb");
+  //   lambda_n = 1/3 lambda (accumulated in place below)
+  WCNS_HIP(launch_lincomb(lambda, lambda, 1.0 / 3.0, tmp, 0.0, nullptr, 0.0, len, s), "lincomb");
+  // Stage 2: U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1).
+  //   l1 = 1/4 l2 + 1/4 dt J(U1)^T l2 ; lambda_n += 3/4 l2
+  WCNS_HIP(launch_zero(tmp, len, s), "zero");
+  if ((st = wcns_residual_adjoint(plan, U1, l2, tmp, work, stream)) != WCNS_OK) return st;
+  WCNS_HIP(launch_lincomb(l1, l2, 0.25, tmp, 0.0, dt_dev, 0.25, len, s), "lincomb");
+  WCNS_HIP(launch_axpy_state(lambda, l2, 0.75, len, s), "axpy");
+  // Stage 1: U1 = Un + dt L(Un).  lambda_n += l1 + dt J(Un)^T l1
+  WCNS_HIP(launch_zero(tmp, len, s), "zero");
+  if ((st = wcns_residual_adjoint(plan, Un, l1, tmp, work, stream)) != WCNS_OK) return st;
+  WCNS_HIP(launch_axpy_state(lambda, l1, 1.0, len, s), "axpy");
+  WCNS_HIP(launch_lincomb(lambda, lambda, 1.0, tmp, 0.0, dt_dev, 1.0, len, s), "lincomb");
+  return WCNS_OK;
+}
+
+wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, void* stream) {
+  g_err.clear();
+  if (!plan || !U || !work) return fail(WCNS_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)work;
+  double* out = (double*)(w + plan->off_W1);
+  hipEvent_t e0, e1;
+  WCNS_HIP(hipEventCreate(&e0), "event");
+  WCNS_HIP(hipEventCreate(&e1), "event");
+  auto time_sweep = [&](int d, float* ms) -> wcns_status {
+    SweepArgs a;
+    sweep_common(plan, d, &a);
+    a.U = U;
+    a.out = out;
+    a.Rin = out;
+    // one warm-up, then three timed launches
+    for (int r = 0; r < 4; ++r) {
+      if (r == 1) WCNS_HIP(hipEventRecord(e0, s), "event record");
+      WCNS_HIP(run_sweep(plan, d, a, MODE_RES, s), "autotune launch");
+    }
+    WCNS_HIP(hipEventRecord(e1, s), "event record");
+    WCNS_HIP(hipEventSynchronize(e1), "event sync");
+    WCNS_HIP(hipEventElapsedTime(ms, e0, e1), "event time");
+    return WCNS_OK;
+  };
+  wcns_status st = WCNS_OK;
+  float best = 1e30f;
+  int best_tm = plan->tm;
+  for (int tm : kTmCandidates) {
+    plan->tm = tm;
+    float ms;
+    if ((st = time_sweep(0, &ms)) != WCNS_OK) break;
+    if (ms < best) {
+      best = ms;
+      best_tm = tm;
+    }
+  }
+  plan->tm = best_tm;
+  if (st == WCNS_OK && plan->d.ndim > 1) {
+    best = 1e30f;
+    int bs = plan->seg, bb = plan->bw;
+    for (int seg : kSegCandidates)
+      for (int bw : kBwCandidates) {
+        plan->seg = seg;
+        plan->bw = bw;
+        float ms;
+        if ((st = time_sweep(1, &ms)) != WCNS_OK) break;
+        if (ms < best) {
+          best = ms;
+          bs = seg;
+          bb = bw;
+        }
+      }
+    plan->seg = bs;
+    plan->bw = bb;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != WCNS_OK) return st;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  TuneKey k{plan->d.ndim, plan->nv, plan->d.weights, plan->d.diff, plan->d.char_proj,
+            plan->d.n[0], plan->d.n[1], plan->d.n[2]};
+  g_tune_cache[k] = std::make_tuple(plan->tm, plan->seg, plan->bw);
+  return WCNS_OK;
+}
+
+// ------------------------------------------------------------------ batch --
+
+static wcns_status batch_build_tiles(wcns_batch_plan* B) {
+  const int TL = B->tm - (B->d.diff ? 5 : 3);
+  struct T { int32_t p, i0, len; };
+  std::vector<T> tiles;
+  for (int64_t p = 0; p < B->nprob; ++p) {
+    const int64_t N = B->h_offset[p + 1] - B->h_offset[p];
+    for (int64_t i0 = 0; i0 < N; i0 += TL)
+      tiles.push_back(T{(int32_t)p, (int32_t)i0, (int32_t)std::min<int64_t>(TL, N - i0)});
+  }
+  // Longest-first: full tiles before the ragged last tile of each problem.
+  std::stable_sort(tiles.begin(), tiles.end(), [](const T& a, const T& b) { return a.len > b.len; });
+  std::vector<int32_t> tp(tiles.size()), ti(tiles.size());
+  for (size_t k = 0; k < tiles.size(); ++k) {
+    tp[k] = tiles[k].p;
+    ti[k] = tiles[k].i0;
+  }
+  if (B->d_tile_prob) hipFree(B->d_tile_prob);
+  if (B->d_tile_i0) hipFree(B->d_tile_i0);
+  B->d_tile_prob = nullptr;
+  B->d_tile_i0 = nullptr;
+  B->ntiles = (int32_t)tiles.size();
+  WCNS_HIP(hipMalloc(&B->d_tile_prob, sizeof(int32_t) * tiles.size()), "hipMalloc tiles");
+  WCNS_HIP(hipMalloc(&B->d_tile_i0, sizeof(int32_t) * tiles.size()), "hipMalloc tiles");
+  WCNS_HIP(hipMemcpy(B->d_tile_prob, tp.data(), sizeof(int32_t) * tp.size(), hipMemcpyHostToDevice), "copy tiles");
+  WCNS_HIP(hipMemcpy(B->d_tile_i0, ti.data(), sizeof(int32_t) * ti.size(), hipMemcpyHostToDevice), "copy tiles");
+  // Persistent grid: enough resident workgroups to fill every CU a few times.
+  B->grid = std::min<int64_t>(B->ntiles, (int64_t)B->cus * 8);
+  if (B->exec) {
+    hipGraphExecDestroy(B->exec);
+    B->exec = nullptr;
+  }
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_plan_create(const wcns_desc* proto, int64_t nprob, const int64_t* offsets_host,
+                                   const double* h_host, wcns_batch_plan** plan) {
+  g_err.clear();
+  if (!plan) return fail(WCNS_EINVAL, "plan is NULL");
+  *plan = nullptr;
+  wcns_status st = validate(proto, true);
+  if (st != WCNS_OK) return st;
+  if (nprob < 1 || nprob > (1 << 30)) return fail(WCNS_EINVAL, "nprob %lld out of range", (long long)nprob);
+  if (!offsets_host || !h_host) return fail(WCNS_EINVAL, "NULL offsets or h");
+  if (offsets_host[0] != 0) return fail(WCNS_EINVAL, "offsets[0] must be 0");
+  for (int64_t p = 0; p < nprob; ++p) {
+    const int64_t N = offsets_host[p + 1] - offsets_host[p];
+    if (N < 9) return fail(WCNS_EINVAL, "problem %lld has %lld < 9 nodes", (long long)p, (long long)N);
+    if (N > (1 << 30)) return fail(WCNS_EINVAL, "problem %lld too long", (long long)p);
+    if (!(h_host[p] > 0.0) || !std::isfinite(h_host[p]))
+      return fail(WCNS_EINVAL, "h[%lld] must be > 0", (long long)p);
+  }
+  wcns_batch_plan* B = new (std::nothrow) wcns_batch_plan();
+  if (!B) return fail(WCNS_ENOMEM, "host allocation failed");
+  B->d = *proto;
+  B->nprob = nprob;
+  B->total = offsets_host[nprob];
+  B->h_offset.assign(offsets_host, offsets_host + nprob + 1);
+  B->h_ih.resize(nprob);
+  for (int64_t p = 0; p < nprob; ++p) B->h_ih[p] = 1.0 / h_host[p];
+  interp_params(proto, &B->ip);
+  B->cus = device_cus();
+  auto cleanup = [&](wcns_status s) {
+    wcns_batch_plan_destroy(B);
+    return s;
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&B->d_offset, sizeof(int64_t) * (nprob + 1))) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = hipMalloc(&B->d_ih, sizeof(double) * nprob)) != hipSuccess) return cleanup(hip_fail(e, "hipMalloc"));
+  if ((e = hipMemcpy(B->d_offset, B->h_offset.data(), sizeof(int64_t) * (nprob + 1), hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy"));
+  if ((e = hipMemcpy(B->d_ih, B->h_ih.data(), sizeof(double) * nprob, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMemcpy"));
+  if ((st = batch_build_tiles(B)) != WCNS_OK) return cleanup(st);
+  const size_t state = sizeof(double) * 3 * B->total;
+  size_t o = 0;
+  B->off_W1 = o; o += align256(state);
+  B->off_W2 = o; o += align256(state);
+  B->off_dtp = o; o += align256(sizeof(double) * nprob);
+  B->bytes = o;
+  *plan = B;
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_plan_destroy(wcns_batch_plan* B) {
+  if (!B) return WCNS_OK;
+  if (B->exec) hipGraphExecDestroy(B->exec);
+  if (B->cap_stream) hipStreamDestroy(B->cap_stream);
+  if (B->d_offset) hipFree(B->d_offset);
+  if (B->d_ih) hipFree(B->d_ih);
+  if (B->d_tile_prob) hipFree(B->d_tile_prob);
+  if (B->d_tile_i0) hipFree(B->d_tile_i0);
+  delete B;
+  return WCNS_OK;
+}
+
+int64_t wcns_batch_state_elems(const wcns_batch_plan* B) { return B ? 3 * B->total : 0; }
+size_t wcns_batch_workspace_bytes(const wcns_batch_plan* B) { return B ? B->bytes : 0; }
+
+static void batch_args(const wcns_batch_plan* B, double* dtp, SweepArgs* a, BatchArgs* b) {
+  std::memset(a, 0, sizeof *a);
+  std::memset(b, 0, sizeof *b);
+  a->npts = B->total;
+  a->n[0] = B->total;
+  a->n[1] = a->n[2] = 1;
+  a->bc = B->d.bc[0];
+  a->diff = B->d.diff;
+  a->ih = 0.0;
+  a->ip = B->ip;
+  a->pp.gamma = B->d.gamma;
+  a->pp.adv = 0.0;
+  a->pp.charproj = B->d.char_proj;
+  b->offset = B->d_offset;
+  b->ih = B->d_ih;
+  b->dtp = dtp;
+  b->tile_prob = B->d_tile_prob;
+  b->tile_i0 = B->d_tile_i0;
+  b->ntiles = B->ntiles;
+  b->nprob = (int32_t)B->nprob;
+}
+
+wcns_status wcns_batch_residual(wcns_batch_plan* B, const double* U, double* R, void* work, void* stream) {
+  g_err.clear();
+  (void)work;
+  if (!B || !U || !R) return fail(WCNS_EINVAL, "NULL argument");
+  if (U == R) return fail(WCNS_EINVAL, "U and R must not overlap");
+  SweepArgs a;
+  BatchArgs b;
+  batch_args(B, nullptr, &a, &b);
+  a.U = U;
+  a.out = R;
+  WCNS_HIP(launch_batch_xsweep(a, b, MODE_RES, B->tm, B->grid, (hipStream_t)stream), "batch residual launch");
+  return WCNS_OK;
+}
+
+static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work, double* t_dev,
+                                      double t_end, double cfl, int32_t* status, hipStream_t s) {
+  char* w = (char*)work;
+  double* W1 = (double*)(w + B->off_W1);
+  double* W2 = (double*)(w + B->off_W2);
+  double* dtp = (double*)(w + B->off_dtp);
+  SweepArgs a;
+  BatchArgs b;
+  batch_args(B, dtp, &a, &b);
+  WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl, s), "batch cfl launch");
+  a.status = status;
+  a.U0 = U;
+  const double* src[3] = {U, W1, W2};
+  double* dst[3] = {W1, W2, U};
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int k = 0; k < 3; ++k) {
+    a.U = src[k];
+    a.out = dst[k];
+    a.ca = ca[k];
+    a.cb = cb[k];
+    WCNS_HIP(launch_batch_xsweep(a, b, MODE_STAGE, B->tm, B->grid, s), "batch stage launch");
+  }
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_rk3_step(wcns_batch_plan* B, double* U, void* work, double* t_dev, double t_end,
+                                double cfl, int32_t* status_dev, void* stream) {
+  g_err.clear();
+  if (!B || !U || !work || !t_dev) return fail(WCNS_EINVAL, "NULL argument");
+  if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0");
+  if (!std::isfinite(t_end)) return fail(WCNS_EINVAL, "t_end must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  if (!B->use_graph) return batch_step_enqueue(B, U, work, t_dev, t_end, cfl, status_dev, s);
+  auto key = std::make_tuple((const void*)U, (const void*)work, (const void*)t_dev, t_end, cfl,
+                             (const void*)status_dev, B->tm);
+  if (!B->exec || key != B->key) {
+    if (B->exec) {
+      hipGraphExecDestroy(B->exec);
+      B->exec = nullptr;
+    }
+    if (!B->cap_stream) WCNS_HIP(hipStreamCreateWithFlags(&B->cap_stream, hipStreamNonBlocking), "stream create");
+    WCNS_HIP(hipStreamBeginCapture(B->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    wcns_status st = batch_step_enqueue(B, U, work, t_dev, t_end, cfl, status_dev, B->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(B->cap_stream, &g);
+    if (st != WCNS_OK) {
+      if (g) hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      B->exec = nullptr;
+      return hip_fail(e, "graph instantiate");
+    }
+    B->key = key;
+  }
+  WCNS_HIP(hipGraphLaunch(B->exec, s), "graph launch");
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_set_graph(wcns_batch_plan* B, int32_t enable) {
+  g_err.clear();
+  if (!B) return fail(WCNS_EINVAL, "NULL plan");
+  B->use_graph = enable != 0;
+  return WCNS_OK;
+}
+
+int32_t wcns_batch_get_tile(const wcns_batch_plan* B) { return B ? B->tm : 0; }
+
+wcns_status wcns_batch_set_tile(wcns_batch_plan* B, int32_t tile) {
+  g_err.clear();
+  if (!B) return fail(WCNS_EINVAL, "NULL plan");
+  if (!in_list(tile, kTmCandidates, 3)) return fail(WCNS_EINVAL, "tile %d not among the candidates", tile);
+  if (tile == B->tm) return WCNS_OK;
+  B->tm = tile;
+  return batch_build_tiles(B);
+}
+
+wcns_status wcns_batch_autotune(wcns_batch_plan* B, const double* U, void* work, void* stream) {
+  g_err.clear();
+  if (!B || !U || !work) return fail(WCNS_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)work;
+  double* out = (double*)(w + B->off_W1);
+  hipEvent_t e0, e1;
+  WCNS_HIP(hipEventCreate(&e0), "event");
+  WCNS_HIP(hipEventCreate(&e1), "event");
+  float best = 1e30f;
+  int best_tm = B->tm;
+  wcns_status st = WCNS_OK;
+  for (int tm : kTmCandidates) {
+    if ((st = wcns_batch_set_tile(B, tm)) != WCNS_OK) break;
+    SweepArgs a;
+    BatchArgs b;
+    batch_args(B, nullptr, &a, &b);
+    a.U = U;
+    a.out = out;
+    for (int r = 0; r < 4 && st == WCNS_OK; ++r) {
+      if (r == 1 && hipEventRecord(e0, s) != hipSuccess) st = fail(WCNS_EDEVICE, "event record");
+      hipError_t e = launch_batch_xsweep(a, b, MODE_RES, B->tm, B->grid, s);
+      if (e != hipSuccess) st = hip_fail(e, "autotune launch");
+    }
+    if (st != WCNS_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(WCNS_EDEVICE, "event timing");
+      break;
+    }
+    if (ms < best) {
+      best = ms;
+      best_tm = tm;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != WCNS_OK) return st;
+  return wcns_batch_set_tile(B, best_tm);
+}
+
+const char* wcns_status_string(wcns_status s) {
+  switch (s) {
+    case WCNS_OK: return "ok";
+    case WCNS_EINVAL: return "invalid argument";
+    case WCNS_ENOMEM: return "out of memory";
+    case WCNS_EDEVICE: return "HIP runtime error";
+    case WCNS_ENONPHYS: return "non-physical state";
+    case WCNS_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* wcns_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

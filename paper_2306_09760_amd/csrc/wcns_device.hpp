@@ -1,0 +1,375 @@
+// Device arithmetic of the WCNS-FE residual for gfx950 (FP64 VALU).
+//
+// Everything here is a __device__ inline function used by the sweep, batch
+// and adjoint kernels.  The formulas follow arXiv 2306.09760:
+//   smoothness indicators          eq. 9-10
+//   JS weights                     eq. 11  (denominator (IS + eps)^2)
+//   Z weights                      eq. 14-15 (integer exponent p)
+//   FE mapping                     eq. 20-21 with the coefficient table of
+//                                  Sec. 3.1, applied to the Z weights and
+//                                  renormalised
+//   PFE switch                     App. A (inclusive band)
+//   candidate interpolations       eq. 5, combined per eq. 6
+//   Euler flux                     eq. 32 (extended to 2D/3D)
+// The characteristic projection (Roe-averaged eigenvectors of the
+// direction-normal Jacobian) and the local Lax-Friedrichs midpoint flux are
+// the readings chosen where the paper only says "approximate Riemann
+// solution".
+//
+// Cost notes (the path is bound by FP64 VALU issue, not by HBM):
+//  * the projection uses the sparsity of the Euler eigenvectors: one shared
+//    scalar theta = b2*rho - b1*(u.m) + b1*E per node instead of a dense
+//    nv x nv product;
+//  * reciprocals are v_rcp_f64 refined by two Newton steps;
+//  * tanh returns +-1 without evaluation once |x| >= 20 (tanh(x) rounds to
+//    +-1 in FP64 for |x| > 19.06), which at large steepness xi covers almost
+//    every call.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wcns {
+
+// Weight choice codes (same values as wcns_weights in wcns.h).
+enum : int { WJS = 0, WZ = 1, WFE = 2, WPFE = 3, WLIN = 4 };
+
+// Uniform parameters of the interpolation, passed by value to kernels.
+struct InterpParams {
+  double eps;       // eq. 11 / eq. 14
+  double xi;        // steepness of eq. 20
+  double cv;        // PFE band (App. A)
+  double nu[10];    // null points kappa*(psi_{i,j} + psi_{i,j-1}):
+                    //   g0: nu[0..2], g1: nu[3..6], g2: nu[7..9]
+  int weights;      // WJS .. WLIN
+  int zpow;         // exponent p of eq. 14 (1..4)
+};
+
+// Physics parameters of one sweep.
+struct PhysParams {
+  double gamma;     // Euler
+  double adv;       // advection speed along the sweep direction
+  int charproj;     // 1 = characteristic projection
+};
+
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  return r;
+}
+
+// tanh(x) = sign(x) * expm1(2|x|) / (expm1(2|x|) + 2).
+__device__ __forceinline__ double tanh_sat(double x) {
+  double ax = __builtin_fabs(x);
+  double r = 1.0;
+  if (ax < 20.0) {
+    double e = expm1(2.0 * ax);
+    r = e * rcp(e + 2.0);
+  }
+  return __builtin_copysign(r, x);
+}
+
+// Ideal weights d_k (Sec. 2).
+constexpr double D0 = 1.0 / 16.0, D1 = 10.0 / 16.0, D2 = 5.0 / 16.0;
+
+// g_i of eq. 20.  phi(i,j) * tanh(xi * phi(i,j) * x) = tanh(xi * x) because
+// tanh is odd and phi = +-1, so the sign table of eq. 21 folds away.  The
+// amplitudes (omega_{i,j} - omega_{i,j-1}) / 2 come from the coefficient
+// table; entries equal to the argument make the amplitude depend on w.
+__device__ __forceinline__ double fe_g0(double w, const InterpParams& P) {
+  double g = w;
+  g += 0.5 * (D0 - w) * tanh_sat(P.xi * (w - P.nu[0]));
+  g += 0.5 * (1.0 / 6.0 - D0) * tanh_sat(P.xi * (w - P.nu[1]));
+  g += 0.5 * (w - 1.0 / 6.0) * tanh_sat(P.xi * (w - P.nu[2]));
+  return g;
+}
+__device__ __forceinline__ double fe_g1(double w, const InterpParams& P) {
+  double g = w;
+  g += 0.5 * (D1 - w) * tanh_sat(P.xi * (w - P.nu[3]));
+  g += 0.5 * (0.5 - D1) * tanh_sat(P.xi * (w - P.nu[4]));
+  g += 0.5 * (5.0 / 6.0 - 0.5) * tanh_sat(P.xi * (w - P.nu[5]));
+  g += 0.5 * (w - 5.0 / 6.0) * tanh_sat(P.xi * (w - P.nu[6]));
+  return g;
+}
+__device__ __forceinline__ double fe_g2(double w, const InterpParams& P) {
+  double g = w;
+  g += 0.5 * (D2 - w) * tanh_sat(P.xi * (w - P.nu[7]));
+  g += 0.5 * (0.5 - D2) * tanh_sat(P.xi * (w - P.nu[8]));
+  g += 0.5 * (w - 0.5) * tanh_sat(P.xi * (w - P.nu[9]));
+  return g;
+}
+
+// Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
+// u_{i+2}) = (a, b, c, e, f).
+__device__ __forceinline__ double interp5(const InterpParams& P, double a, double b, double c,
+                                          double e, double f) {
+  // Candidates, eq. 5.
+  const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
+  const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
+  const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
+  if (P.weights == WLIN) return D0 * c0 + D1 * c1 + D2 * c2;
+
+  // Smoothness indicators, eq. 9-10.
+  const double f0 = 0.5 * (a - 4.0 * b + 3.0 * c), s0 = a - 2.0 * b + c;
+  const double f1 = 0.5 * (e - b), s1 = b - 2.0 * c + e;
+  const double f2 = 0.5 * (-3.0 * c + 4.0 * e - f), s2 = c - 2.0 * e + f;
+  const double IS0 = f0 * f0 + s0 * s0;
+  const double IS1 = f1 * f1 + s1 * s1;
+  const double IS2 = f2 * f2 + s2 * s2;
+
+  double a0, a1, a2;
+  if (P.weights == WJS) {
+    const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
+    a0 = D0 * r0 * r0;
+    a1 = D1 * r1 * r1;
+    a2 = D2 * r2 * r2;
+  } else {
+    const double tau = __builtin_fabs(IS0 - IS2);
+    double q0 = tau * rcp(IS0 + P.eps), q1 = tau * rcp(IS1 + P.eps), q2 = tau * rcp(IS2 + P.eps);
+    double p0 = q0, p1 = q1, p2 = q2;
+    for (int k = 1; k < P.zpow; ++k) {
+      p0 *= q0;
+      p1 *= q1;
+      p2 *= q2;
+    }
+    a0 = D0 * (1.0 + p0);
+    a1 = D1 * (1.0 + p1);
+    a2 = D2 * (1.0 + p2);
+  }
+  const double inv = rcp(a0 + a1 + a2);
+  double w0 = a0 * inv, w1 = a1 * inv, w2 = a2 * inv;
+
+  bool map = (P.weights == WFE);
+  if (P.weights == WPFE) {
+    const bool inside = __builtin_fabs(w0 - D0) <= P.cv && __builtin_fabs(w1 - D1) <= P.cv &&
+                        __builtin_fabs(w2 - D2) <= P.cv;
+    map = !inside;
+  }
+  if (map) {
+    const double g0 = fe_g0(w0, P), g1 = fe_g1(w1, P), g2 = fe_g2(w2, P);
+    const double ginv = rcp(g0 + g1 + g2);
+    w0 = g0 * ginv;
+    w1 = g1 * ginv;
+    w2 = g2 * ginv;
+  }
+  return w0 * c0 + w1 * c1 + w2 * c2;
+}
+
+// ------------------------------------------------------------------ Euler --
+// State layout in registers: [rho, m_0 .. m_{ND-1}, E].
+
+template <int ND>
+struct Prim {
+  double ir;        // 1/rho
+  double vel[ND];
+  double p;
+};
+
+template <int ND>
+__device__ __forceinline__ Prim<ND> primitives(const double* U, double gamma) {
+  Prim<ND> q;
+  q.ir = rcp(U[0]);
+  double mm = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    q.vel[k] = U[1 + k] * q.ir;
+    mm += U[1 + k] * q.vel[k];
+  }
+  q.p = (gamma - 1.0) * (U[ND + 1] - 0.5 * mm);
+  return q;
+}
+
+// Physical flux along DIR (eq. 32).
+template <int ND, int DIR>
+__device__ __forceinline__ void euler_flux(const double* U, double gamma, double* F) {
+  const Prim<ND> q = primitives<ND>(U, gamma);
+  const double vn = q.vel[DIR];
+  F[0] = U[1 + DIR];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) F[1 + k] = U[1 + k] * vn + (k == DIR ? q.p : 0.0);
+  F[ND + 1] = (U[ND + 1] + q.p) * vn;
+}
+
+// Roe-averaged quantities that define the eigenvectors between two nodes.
+template <int ND>
+struct RoeState {
+  double vel[ND];
+  double H, c, ic, q2h, b1, b2;   // q2h = |u|^2 / 2
+};
+
+template <int ND>
+__device__ __forceinline__ RoeState<ND> roe_average(const double* UA, const double* UB,
+                                                    double gamma) {
+  const Prim<ND> A = primitives<ND>(UA, gamma);
+  const Prim<ND> B = primitives<ND>(UB, gamma);
+  const double sA = __builtin_sqrt(UA[0]), sB = __builtin_sqrt(UB[0]);
+  const double den = rcp(sA + sB);
+  const double wA = sA * den, wB = sB * den;
+  RoeState<ND> r;
+  double q2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    r.vel[k] = wA * A.vel[k] + wB * B.vel[k];
+    q2 += r.vel[k] * r.vel[k];
+  }
+  const double HA = (UA[ND + 1] + A.p) * A.ir;
+  const double HB = (UB[ND + 1] + B.p) * B.ir;
+  r.H = wA * HA + wB * HB;
+  r.q2h = 0.5 * q2;
+  r.c = __builtin_sqrt((gamma - 1.0) * (r.H - r.q2h));
+  r.ic = rcp(r.c);
+  r.b1 = (gamma - 1.0) * r.ic * r.ic;
+  r.b2 = r.q2h * r.b1;
+  return r;
+}
+
+// Characteristic field order: 0 = (u_n - c), 1 = entropy, 2 .. ND = shear
+// along the tangential axes in increasing order, ND + 1 = (u_n + c).
+template <int ND, int DIR>
+__device__ __forceinline__ int tangential_axis(int t) {
+  // t-th axis other than DIR
+  return (t < DIR) ? t : t + 1;
+}
+
+// Left eigenvectors applied to one node U: W = L U.
+template <int ND, int DIR>
+__device__ __forceinline__ void project(const RoeState<ND>& r, const double* U, double* W) {
+  double um = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) um += r.vel[k] * U[1 + k];
+  const double theta = r.b2 * U[0] - r.b1 * um + r.b1 * U[ND + 1];
+  const double an = (r.vel[DIR] * U[0] - U[1 + DIR]) * r.ic;
+  W[0] = 0.5 * (theta + an);
+  W[1] = U[0] - theta;
+#pragma unroll
+  for (int t = 0; t < ND - 1; ++t) {
+    const int ax = tangential_axis<ND, DIR>(t);
+    W[2 + t] = U[1 + ax] - r.vel[ax] * U[0];
+  }
+  W[ND + 1] = 0.5 * (theta - an);
+}
+
+// Right eigenvectors applied to characteristic values: U = R W.
+template <int ND, int DIR>
+__device__ __forceinline__ void unproject(const RoeState<ND>& r, const double* W, double* U) {
+  const double sum = W[0] + W[1] + W[ND + 1];
+  const double dif = W[ND + 1] - W[0];
+  U[0] = sum;
+  double E = r.H * (W[0] + W[ND + 1]) + r.vel[DIR] * r.c * dif + r.q2h * W[1];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) U[1 + k] = r.vel[k] * sum;
+  U[1 + DIR] += r.c * dif;
+#pragma unroll
+  for (int t = 0; t < ND - 1; ++t) {
+    const int ax = tangential_axis<ND, DIR>(t);
+    U[1 + ax] += W[2 + t];
+    E += r.vel[ax] * W[2 + t];
+  }
+  U[ND + 1] = E;
+}
+
+// Local Lax-Friedrichs flux between the interpolated states UL and UR.
+template <int ND, int DIR>
+__device__ __forceinline__ void llf_flux(const double* UL, const double* UR, double gamma,
+                                         double* F) {
+  constexpr int NV = ND + 2;
+  double FL[NV], FR[NV];
+  const Prim<ND> L = primitives<ND>(UL, gamma);
+  const Prim<ND> R = primitives<ND>(UR, gamma);
+  const double cL = __builtin_sqrt(gamma * L.p * L.ir);
+  const double cR = __builtin_sqrt(gamma * R.p * R.ir);
+  const double lamL = __builtin_fabs(L.vel[DIR]) + cL;
+  const double lamR = __builtin_fabs(R.vel[DIR]) + cR;
+  const double alpha = (lamL >= lamR) ? lamL : lamR;
+  FL[0] = UL[1 + DIR];
+  FR[0] = UR[1 + DIR];
+#pragma unroll
+  for (int k = 0; k < ND; ++k) {
+    FL[1 + k] = UL[1 + k] * L.vel[DIR] + (k == DIR ? L.p : 0.0);
+    FR[1 + k] = UR[1 + k] * R.vel[DIR] + (k == DIR ? R.p : 0.0);
+  }
+  FL[ND + 1] = (UL[ND + 1] + L.p) * L.vel[DIR];
+  FR[ND + 1] = (UR[ND + 1] + R.p) * R.vel[DIR];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * alpha * (UR[v] - UL[v]);
+}
+
+// Numerical flux at the midpoint between nodes s[2] and s[3] of a six-node
+// stencil s[0..5] (nodes m-2 .. m+3) along DIR.  NV = 1: scalar advection.
+template <int NV, int DIR>
+__device__ __forceinline__ void midpoint_flux(const InterpParams& IP, const PhysParams& PP,
+                                              const double (&s)[6][NV], double (&F)[NV]) {
+  if constexpr (NV == 1) {
+    const double uL = interp5(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0]);
+    const double uR = interp5(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0]);
+    F[0] = 0.5 * PP.adv * (uL + uR) - 0.5 * __builtin_fabs(PP.adv) * (uR - uL);
+  } else {
+    constexpr int ND = NV - 2;
+    double WL[NV], WR[NV], UL[NV], UR[NV];
+    if (PP.charproj) {
+      const RoeState<ND> r = roe_average<ND>(s[2], s[3], PP.gamma);
+      double W[6][NV];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) project<ND, DIR>(r, s[j], W[j]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        WL[v] = interp5(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
+        WR[v] = interp5(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
+      }
+      unproject<ND, DIR>(r, WL, UL);
+      unproject<ND, DIR>(r, WR, UR);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UL[v] = interp5(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
+        UR[v] = interp5(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
+      }
+    }
+    llf_flux<ND, DIR>(UL, UR, PP.gamma, F);
+  }
+}
+
+// Physical flux at one node along DIR.
+template <int NV, int DIR>
+__device__ __forceinline__ void node_flux(const PhysParams& PP, const double (&U)[NV],
+                                          double (&F)[NV]) {
+  if constexpr (NV == 1) {
+    F[0] = PP.adv * U[0];
+  } else {
+    euler_flux<NV - 2, DIR>(U, PP.gamma, F);
+  }
+}
+
+// Sum over directions of (|u_d| + c) / h_d at one node (advection: the
+// caller adds |a_d| / h_d).
+template <int ND>
+__device__ __forceinline__ double wave_rate(const double* U, double gamma, const double* ih) {
+  const Prim<ND> q = primitives<ND>(U, gamma);
+  const double c = __builtin_sqrt(gamma * q.p * q.ir);
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) s += (__builtin_fabs(q.vel[k]) + c) * ih[k];
+  return s;
+}
+
+// True if the state is finite and (Euler) rho > 0 and p > 0.
+template <int NV>
+__device__ __forceinline__ bool physical(const double (&U)[NV], double gamma) {
+  bool ok = true;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ok = ok && __builtin_isfinite(U[v]);
+  if constexpr (NV > 1) {
+    constexpr int ND = NV - 2;
+    double mm = 0.0;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) mm += U[1 + k] * U[1 + k];
+    const double p = (gamma - 1.0) * (U[ND + 1] - 0.5 * mm / U[0]);
+    ok = ok && (U[0] > 0.0) && (p > 0.0);
+  }
+  return ok;
+}
+
+}  // namespace wcns

@@ -1,0 +1,81 @@
+// Internal (non-ABI) declarations shared by the kernel and API translation
+// units of the WCNS-FE library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wcns_device.hpp"
+
+namespace wcns {
+
+enum SweepMode : int { MODE_RES = 0, MODE_ACC = 1, MODE_STAGE = 2 };
+
+// Arguments of one directional sweep.
+struct SweepArgs {
+  const double* U;      // state under the stencil, U^(k)
+  const double* U0;     // U^n (stage mode, ca != 0)
+  const double* Rin;    // residual of earlier sweeps (acc/stage), may be null
+  double* out;          // R (res/acc) or U^(k+1) (stage)
+  const double* dt;     // device dt (stage mode, non-batch)
+  int32_t* status;      // OR-ed bit 0 on a non-physical stage result (may be null)
+  double ca, cb;        // stage: out = ca*U0 + cb*(U + dt*R)
+  int64_t npts;         // stride between variables
+  int64_t n[3];         // grid extents (x, y, z)
+  int32_t bc;           // boundary type along the sweep direction
+  int32_t diff;         // 0 = MND6, 1 = MD6
+  double ih;            // 1/h along the sweep direction
+  InterpParams ip;
+  PhysParams pp;
+};
+
+// Ragged batch description (device arrays).
+struct BatchArgs {
+  const int64_t* offset;   // nprob+1 column offsets
+  const double* ih;        // 1/h per problem
+  double* dtp;             // per-problem dt of the current step (0 = inactive)
+  const int32_t* tile_prob;
+  const int32_t* tile_i0;
+  int32_t ntiles;
+  int32_t nprob;
+};
+
+// Launchers (wcns_kernels.hip).  All enqueue on `stream` and return the
+// hipError_t of the launch.
+hipError_t launch_xsweep(int nv, const SweepArgs& a, int mode, int tm, hipStream_t stream);
+hipError_t launch_march(int nv, int dir, const SweepArgs& a, int mode, int seg, int bw,
+                        hipStream_t stream);
+hipError_t launch_batch_xsweep(const SweepArgs& a, const BatchArgs& b, int mode, int tm,
+                               int grid, hipStream_t stream);
+hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double gamma,
+                      const double* ih, const double* adv, double cfl, double* partial,
+                      int nblocks, double* dt_out, hipStream_t stream);
+hipError_t launch_batch_cfl(const double* U, int64_t total, const BatchArgs& b, double gamma,
+                            double* t, double t_end, double cfl, hipStream_t stream);
+hipError_t launch_axpy_state(double* y, const double* x, double a, int64_t n,
+                             hipStream_t stream);
+hipError_t launch_lincomb(double* out, const double* x, double ax, const double* y, double ay,
+                          const double* dt, double ydt, int64_t n, hipStream_t stream);
+hipError_t launch_zero(double* y, int64_t n, hipStream_t stream);
+
+// Adjoint launchers (wcns_adjoint.hip).
+struct AdjArgs {
+  const double* U;      // state
+  const double* Rbar;   // cotangent of the residual
+  double* contrib;      // per-midpoint contributions: [(m * 6 + k) * NV + v] blocks
+  double* Ubar;         // accumulated cotangent of U
+  double scale;         // Ubar += scale * (dL/dU)^T Rbar
+  int64_t npts;
+  int64_t n[3];
+  int32_t bc;
+  int32_t diff;
+  double ih;
+  InterpParams ip;
+  PhysParams pp;
+};
+hipError_t launch_adjoint_dir(int nv, int dir, const AdjArgs& a, hipStream_t stream);
+size_t adjoint_contrib_elems(int nv, int dir, const int64_t n[3], int diff);
+
+int cfl_blocks(int64_t npts);
+
+}  // namespace wcns

@@ -1,0 +1,202 @@
+"""Python face of the WCNS-FE library: plans over torch device tensors.
+
+PyTorch supplies device memory and the current HIP stream; every arithmetic
+step runs in ``libwcns.so``.  States are float64 tensors shaped
+``(nv, nx)``, ``(nv, ny, nx)`` or ``(nv, nz, ny, nx)`` (contiguous).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _require_device(device):
+    if not torch.cuda.is_available():
+        raise _lib.WCNSError("no HIP device is visible: the WCNS library runs on the GPU only")
+    return torch.device(device)
+
+
+class Plan:
+    """A residual / SSP-RK3 plan for one grid (see include/wcns.h)."""
+
+    def __init__(self, device="cuda", **problem):
+        self.device = _require_device(device)
+        self.problem = dict(problem)
+        self.desc = _lib.make_desc(**problem)
+        h = C.c_void_p()
+        check(lib().wcns_plan_create(C.byref(self.desc), C.byref(h)), "wcns_plan_create")
+        self._h = h
+        self.ndim = self.desc.ndim
+        self.nv = 1 if self.desc.system == 0 else self.ndim + 2
+        n = [self.desc.n[k] for k in range(self.ndim)]
+        self.shape = (self.nv,) + tuple(reversed(n))
+        nbytes = lib().wcns_workspace_bytes(h)
+        self.work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        self.dt = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().wcns_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _check_state(self, U):
+        if U.dtype != torch.float64 or not U.is_contiguous() or U.device != self.device:
+            raise _lib.WCNSError("state must be a contiguous float64 tensor on the plan's device")
+        if tuple(U.shape) != self.shape:
+            raise _lib.WCNSError(f"state shape {tuple(U.shape)} != {self.shape}")
+
+    def residual(self, U, out=None):
+        self._check_state(U)
+        R = torch.empty_like(U) if out is None else out
+        check(lib().wcns_residual(self._h, _ptr(U), _ptr(R), _ptr(self.work), _stream()),
+              "wcns_residual")
+        return R
+
+    def cfl_dt(self, U, cfl=0.5, out=None):
+        self._check_state(U)
+        dt = self.dt if out is None else out
+        check(lib().wcns_cfl_dt(self._h, _ptr(U), cfl, _ptr(dt), _ptr(self.work), _stream()),
+              "wcns_cfl_dt")
+        return dt
+
+    def rk3_step(self, U, dt=None, cfl=0.5, status=None):
+        """In-place SSP-RK3 step; dt: device tensor (1,) or None (cfl-limited)."""
+        self._check_state(U)
+        check(lib().wcns_rk3_step(self._h, _ptr(U), _ptr(self.work), _ptr(dt), cfl,
+                                  _ptr(status), _stream()), "wcns_rk3_step")
+        return U
+
+    def residual_adjoint(self, U, Rbar, Ubar=None):
+        """Ubar += (dL/dU)^T Rbar (Ubar zero-initialised if None)."""
+        self._check_state(U)
+        self._check_state(Rbar)
+        if Ubar is None:
+            Ubar = torch.zeros_like(U)
+        check(lib().wcns_residual_adjoint(self._h, _ptr(U), _ptr(Rbar), _ptr(Ubar),
+                                          _ptr(self.work), _stream()), "wcns_residual_adjoint")
+        return Ubar
+
+    def rk3_step_adjoint(self, Un, lam, dt):
+        self._check_state(Un)
+        self._check_state(lam)
+        check(lib().wcns_rk3_step_adjoint(self._h, _ptr(Un), _ptr(lam), _ptr(self.work),
+                                          _ptr(dt), _stream()), "wcns_rk3_step_adjoint")
+        return lam
+
+    def autotune(self, U):
+        self._check_state(U)
+        check(lib().wcns_plan_autotune(self._h, _ptr(U), _ptr(self.work), _stream()),
+              "wcns_plan_autotune")
+        return self.tiles
+
+    @property
+    def tiles(self):
+        t = (C.c_int32 * 3)()
+        lib().wcns_plan_get_tiles(self._h, t)
+        return tuple(t)
+
+    @tiles.setter
+    def tiles(self, value):
+        t = (C.c_int32 * 3)(*value)
+        check(lib().wcns_plan_set_tiles(self._h, t), "wcns_plan_set_tiles")
+
+
+class BatchPlan:
+    """Ragged batch of independent 1D Euler problems (see include/wcns.h)."""
+
+    def __init__(self, offsets, h, device="cuda", **proto):
+        self.device = _require_device(device)
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        self.nprob = len(offsets) - 1
+        self.total = int(offsets[-1])
+        proto = dict(proto)
+        proto.setdefault("system", "euler")
+        proto.setdefault("bc", "transmissive")
+        proto["ndim"] = 1
+        proto["n"] = (9,)
+        proto["h"] = (1.0,)
+        self.desc = _lib.make_desc(**proto)
+        hd = C.c_void_p()
+        check(lib().wcns_batch_plan_create(
+            C.byref(self.desc), self.nprob, offsets.ctypes.data_as(C.POINTER(C.c_int64)),
+            h.ctypes.data_as(C.POINTER(C.c_double)), C.byref(hd)), "wcns_batch_plan_create")
+        self._h = hd
+        self.shape = (3, self.total)
+        nbytes = lib().wcns_batch_workspace_bytes(hd)
+        self.work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().wcns_batch_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def _check_state(self, U):
+        if U.dtype != torch.float64 or not U.is_contiguous() or U.device != self.device:
+            raise _lib.WCNSError("state must be a contiguous float64 tensor on the plan's device")
+        if tuple(U.shape) != self.shape:
+            raise _lib.WCNSError(f"state shape {tuple(U.shape)} != {self.shape}")
+
+    def residual(self, U, out=None):
+        self._check_state(U)
+        R = torch.empty_like(U) if out is None else out
+        check(lib().wcns_batch_residual(self._h, _ptr(U), _ptr(R), _ptr(self.work), _stream()),
+              "wcns_batch_residual")
+        return R
+
+    def rk3_step(self, U, t, t_end, cfl=0.5, status=None):
+        self._check_state(U)
+        check(lib().wcns_batch_rk3_step(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
+                                        float(cfl), _ptr(status), _stream()), "wcns_batch_rk3_step")
+        return U
+
+    def set_graph(self, enable=True):
+        check(lib().wcns_batch_set_graph(self._h, 1 if enable else 0), "wcns_batch_set_graph")
+
+    def autotune(self, U):
+        self._check_state(U)
+        check(lib().wcns_batch_autotune(self._h, _ptr(U), _ptr(self.work), _stream()),
+              "wcns_batch_autotune")
+        return self.tile
+
+    @property
+    def tile(self):
+        return int(lib().wcns_batch_get_tile(self._h))
+
+    @tile.setter
+    def tile(self, value):
+        check(lib().wcns_batch_set_tile(self._h, int(value)), "wcns_batch_set_tile")
+
+    def run_to_time(self, U, t_end, cfl=0.5, check_every=64, max_steps=10 ** 7, status=None):
+        """Steps every problem to t_end (host checks completion every
+        ``check_every`` steps).  Returns (t, steps issued)."""
+        t = torch.zeros(self.nprob, dtype=torch.float64, device=self.device)
+        steps = 0
+        while steps < max_steps:
+            for _ in range(check_every):
+                self.rk3_step(U, t, t_end, cfl, status)
+            steps += check_every
+            if bool((t >= t_end).all().item()):
+                break
+        return t, steps

@@ -1,0 +1,122 @@
+"""Ragged batch of independent 1D Euler problems (one persistent launch per
+stage, graph-captured step) against the oracle run problem by problem."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import rel_err, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2306_09760_amd import solver
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return solver
+
+
+def _small_batch(W, seed=0, nprob=12, nmin=9, nmax=700):
+    return W.shock_tube_batch(seed=seed, nprob=nprob, nmin=nmin, nmax=nmax)
+
+
+def _oracle(ora, meta, p, **kw):
+    N = int(meta["lengths"][p])
+    return ora.Problem(system="euler", ndim=1, n=(N,), h=(meta["h"][p],), bc="transmissive", **kw)
+
+
+def _cols(U, meta, p):
+    o = meta["offsets"]
+    return U[:, o[p]:o[p + 1]]
+
+
+@pytest.mark.parametrize("weights,xi", [("fe", 100.0), ("fe", 1e6), ("z", 100.0), ("js", 100.0)])
+@pytest.mark.parametrize("tile", [64, 128, 256])
+def test_batch_residual(lib, ora, W, weights, xi, tile):
+    prob, U, meta = _small_batch(W)
+    say("batch residual", weights, xi, tile)
+    B = lib.BatchPlan(meta["offsets"], meta["h"], weights=weights, xi=xi)
+    B.tile = tile
+    R = to_host(B.residual(to_dev(U)))
+    for p in range(len(meta["lengths"])):
+        ref = _oracle(ora, meta, p, weights=weights, xi=xi).residual(_cols(U, meta, p))
+        n, pt = rel_err(_cols(R, meta, p), ref)
+        assert n <= 1e-12 and pt <= 1e-10, (p, n, pt)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_steps_to_time_match_per_problem_runs(lib, ora, W, graph):
+    prob, U, meta = _small_batch(W, seed=1, nprob=10, nmin=64, nmax=300)
+    t_end = 0.05
+    say("batch run to time, graph =", graph)
+    B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+    B.set_graph(graph)
+    Ud = to_dev(U)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    t, steps = B.run_to_time(Ud, t_end, cfl=0.5, check_every=16, status=status)
+    assert bool((t == t_end).all().item())
+    assert int(status.item()) == 0
+    Ug = to_host(Ud)
+    for p in range(len(meta["lengths"])):
+        O = _oracle(ora, meta, p, weights="fe", xi=100.0)
+        Uo, s, tt, bad = O.run_to_time(_cols(U, meta, p), t_end, cfl=0.5)
+        assert bad == 0 and tt == t_end
+        n, pt = rel_err(_cols(Ug, meta, p), Uo)
+        assert n <= 1e-9 and pt <= 1e-9, (p, n, pt)
+
+
+def test_graph_replay_equals_eager_steps(lib, W):
+    prob, U, meta = _small_batch(W, seed=2, nprob=40, nmin=100, nmax=2000)
+    say("graph vs eager")
+    res = []
+    for graph in (False, True):
+        B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+        B.set_graph(graph)
+        Ud = to_dev(U)
+        t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+        out = []
+        for k in range(6):
+            B.rk3_step(Ud, t, 0.2, 0.5)
+            torch.cuda.synchronize()
+            out.append(to_host(Ud).copy())  # eager work between replays
+        res.append(out)
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+def test_finished_problems_are_untouched(lib, W):
+    prob, U, meta = _small_batch(W, seed=3, nprob=6, nmin=50, nmax=80)
+    say("finished problems")
+    B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+    Ud = to_dev(U)
+    t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+    t[2] = 1.0  # already past t_end
+    B.rk3_step(Ud, t, 0.1, 0.5)
+    Ug = to_host(Ud)
+    assert np.array_equal(_cols(Ug, meta, 2), _cols(U, meta, 2))
+    assert not np.array_equal(_cols(Ug, meta, 0), _cols(U, meta, 0))
+
+
+def test_full_config2_batch_sampled(lib, ora, W):
+    """The 4096-problem batch at full size: residual and one step on 48
+    sampled problems (longest, shortest and random) vs the oracle."""
+    prob, U, meta = W.shock_tube_batch(seed=0)
+    L = meta["lengths"]
+    rng = np.random.default_rng(5)
+    sample = sorted(set([int(np.argmax(L)), int(np.argmin(L))] + list(rng.choice(len(L), 46, replace=False))))
+    say("config2 full batch sampled", len(sample))
+    B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+    Ud = to_dev(U)
+    B.autotune(Ud)
+    R = to_host(B.residual(Ud))
+    t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+    B.rk3_step(Ud, t, 0.2, 0.5)
+    Ug = to_host(Ud)
+    for p in sample:
+        O = _oracle(ora, meta, p, weights="fe", xi=100.0)
+        n, pt = rel_err(_cols(R, meta, p), O.residual(_cols(U, meta, p)))
+        assert n <= 1e-12 and pt <= 1e-10, ("residual", p, n, pt)
+        dt = O.cfl_dt(_cols(U, meta, p), 0.5)
+        U1, bad = O.rk3_step(_cols(U, meta, p), dt)
+        n, pt = rel_err(_cols(Ug, meta, p), U1)
+        assert n <= 1e-12 and pt <= 1e-12, ("step", p, n, pt)

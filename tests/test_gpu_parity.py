@@ -1,0 +1,202 @@
+"""Parity of the HIP residual, CFL step and SSP-RK3 step with the CPU oracle,
+element by element on the same seeded inputs (sizes that span several tiles
+and a ragged tail).  Tolerances: normwise relative error per variable
+<= 1e-12 for one residual / one stage; <= 1e-9 after a full run (FP64)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import rel_err, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+STAGE_TOL = 1e-12
+# Isolated points may legitimately differ more where a weight sits within
+# ~1/xi of a mapping null point (the map amplifies a 1-ulp difference by
+# up to xi * amplitude); bounded relative to the largest value.
+POINT_TOL = 1e-10
+RUN_TOL = 1e-9
+
+WEIGHTS = [("js", 100.0), ("z", 100.0), ("fe", 100.0), ("fe", 1e6), ("pfe", 100.0), ("linear", 100.0)]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2306_09760_amd import solver
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return solver
+
+
+def _pair(lib, ora, prob, **kw):
+    return lib.Plan(**prob, **kw), ora.Problem(**prob, **kw)
+
+
+def _check(gpu, ref, tol=STAGE_TOL, ptol=POINT_TOL, what=""):
+    n, p = rel_err(gpu, ref)
+    assert n <= tol and p <= ptol, f"{what}: normwise {n:.3e}, pointwise {p:.3e}"
+
+
+# ------------------------------------------------------------------------ 1D --
+@pytest.mark.parametrize("weights,xi", WEIGHTS)
+@pytest.mark.parametrize("diff", ["mnd6", "md6"])
+def test_residual_advection_config1(lib, ora, W, weights, xi, diff):
+    prob, U, _ = W.advection_sine(seed=0)
+    say("advection residual", weights, xi, diff)
+    G, O = _pair(lib, ora, prob, weights=weights, xi=xi, diff=diff)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="advection")
+
+
+@pytest.mark.parametrize("weights,xi", WEIGHTS)
+@pytest.mark.parametrize("bc", ["transmissive", "periodic"])
+@pytest.mark.parametrize("charproj", [True, False])
+def test_residual_euler1d(lib, ora, W, weights, xi, bc, charproj):
+    prob, U, _ = W.shock_tube(1.0, 0.75, 1.0, 0.125, -0.3, 0.1, 517)
+    prob["bc"] = bc
+    say("euler1d residual", weights, xi, bc, charproj)
+    G, O = _pair(lib, ora, prob, weights=weights, xi=xi, charproj=charproj)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="euler1d")
+
+
+@pytest.mark.parametrize("tm", [64, 128, 256])
+@pytest.mark.parametrize("diff", ["mnd6", "md6"])
+def test_xsweep_tile_shape_invariance(lib, W, tm, diff):
+    """Every tile shape gives bitwise the same residual (halo / LDS checks)."""
+    prob, U, _ = W.shock_tube(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 1000)
+    say("tile invariance", tm, diff)
+    G = lib.Plan(**prob, weights="fe", diff=diff)
+    Ud = to_dev(U)
+    G.tiles = (256, 32, 64)
+    ref = to_host(G.residual(Ud))
+    G.tiles = (tm, 32, 64)
+    assert np.array_equal(to_host(G.residual(Ud)), ref)
+
+
+# ------------------------------------------------------------------------ 2D --
+@pytest.mark.parametrize("weights,xi", WEIGHTS)
+@pytest.mark.parametrize("diff", ["mnd6", "md6"])
+def test_residual_riemann2d(lib, ora, W, weights, xi, diff):
+    prob, U, _ = W.riemann2d(seed=0, n=70)
+    prob["n"] = (70, 70)
+    say("riemann2d residual", weights, xi, diff)
+    G, O = _pair(lib, ora, prob, weights=weights, xi=xi, diff=diff)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="riemann2d")
+
+
+@pytest.mark.parametrize("seg,bw", [(16, 64), (32, 128), (64, 256)])
+def test_residual_2d_rectangular_and_march_shapes(lib, ora, W, seg, bw):
+    """Non-square grid, periodic in x and transmissive in y, several march
+    segment / lane shapes."""
+    prob, U = W.random_smooth_state(4, 2, (77, 45), amp=0.3)
+    U = U.copy()
+    U[0, 10:30, 20:50] *= 2.0  # a density block with sharp edges
+    prob["bc"] = ("periodic", "transmissive")
+    say("2d rect", seg, bw)
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0)
+    G.tiles = (128, seg, bw)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="2d rect")
+
+
+def test_residual_advection_2d(lib, ora):
+    n = (40, 33)
+    x = np.arange(n[0]) / n[0]
+    y = np.arange(n[1]) / n[1]
+    X, Y = np.meshgrid(x, y)
+    U = np.where((X - 0.5) ** 2 + (Y - 0.5) ** 2 < 0.05, 1.0, 0.0)[None] + 0.1 * np.sin(2 * np.pi * X)[None]
+    prob = dict(system="advection", ndim=2, n=n, adv=(1.0, -0.7), bc="periodic")
+    say("advection 2d")
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="advection2d")
+
+
+# ------------------------------------------------------------------------ 3D --
+@pytest.mark.parametrize("weights,xi", [("fe", 100.0), ("z", 100.0), ("fe", 1e6), ("js", 100.0)])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+def test_residual_turbulence3d(lib, ora, W, weights, xi, bc):
+    prob, U, _ = W.turbulence3d(seed=0, n=20)
+    prob["bc"] = bc
+    say("turbulence3d residual", weights, xi, bc)
+    G, O = _pair(lib, ora, prob, weights=weights, xi=xi)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="turbulence3d")
+
+
+def test_residual_3d_rectangular_md6(lib, ora, W):
+    prob, U = W.random_smooth_state(6, 3, (23, 17, 19), amp=0.3)
+    U = U.copy()
+    U[0, :, 5:9, :] *= 1.7
+    prob["bc"] = ("transmissive", "periodic", "transmissive")
+    say("3d rect md6")
+    G, O = _pair(lib, ora, prob, weights="pfe", xi=100.0, diff="md6")
+    G.tiles = (64, 16, 64)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="3d md6")
+
+
+# ------------------------------------------------------------ CFL and RK3 ----
+@pytest.mark.parametrize("case", ["adv1d", "tube", "riemann2d", "turb3d"])
+def test_cfl_dt_and_one_rk3_step(lib, ora, W, case):
+    if case == "adv1d":
+        prob, U, _ = W.advection_sine(seed=3)
+    elif case == "tube":
+        prob, U, _ = W.shock_tube(1.0, 0.75, 1.0, 0.125, 0.0, 0.1, 300)
+    elif case == "riemann2d":
+        prob, U, _ = W.riemann2d(seed=2, n=48)
+    else:
+        prob, U, _ = W.turbulence3d(seed=1, n=16)
+    say("cfl + rk3 step", case)
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0)
+    Ud = to_dev(U)
+    dt = to_host(G.cfl_dt(Ud, 0.5))[0]
+    dt_ref = O.cfl_dt(U, 0.5)
+    assert dt == pytest.approx(dt_ref, rel=1e-14)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    G.rk3_step(Ud, dt=None, cfl=0.5, status=status)
+    U1, bad = O.rk3_step(U, dt_ref)
+    assert bad == 0 and int(status.item()) == 0
+    _check(to_host(Ud), U1, what=f"rk3 {case}")
+
+
+def test_config1_full_run(lib, ora, W):
+    """Config 1 to t = 2 (400 steps of dt = 0.005) with FE at the paper's
+    xi = 100: GPU vs oracle after the whole run."""
+    prob, U, meta = W.advection_sine(seed=0)
+    say("config1 full run")
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0)
+    Ud = to_dev(U)
+    dt = torch.full((1,), 0.005, dtype=torch.float64, device="cuda")
+    for _ in range(400):
+        G.rk3_step(Ud, dt=dt)
+    Uo, bad = O.run_steps(U, 400, dt=0.005)
+    _check(to_host(Ud), Uo, tol=RUN_TOL, ptol=RUN_TOL, what="config1 run")
+
+
+def test_riemann2d_multi_step_run(lib, ora, W):
+    prob, U, _ = W.riemann2d(seed=0, n=64)
+    say("riemann2d 20 steps")
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0)
+    Ud = to_dev(U)
+    for _ in range(20):
+        G.rk3_step(Ud, cfl=0.5)
+    Uo, bad = O.run_steps(U, 20, cfl=0.5)
+    _check(to_host(Ud), Uo, tol=RUN_TOL, ptol=RUN_TOL, what="riemann2d run")
+
+
+def test_status_word_flags_nonphysical_state(lib, W):
+    prob, U, _ = W.shock_tube(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 64)
+    U = U.copy()
+    U[2, 30] = -1.0  # negative energy -> negative pressure
+    say("status word")
+    G = lib.Plan(**prob, weights="fe")
+    Ud = to_dev(U)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dt = torch.full((1,), 1e-4, dtype=torch.float64, device="cuda")
+    G.rk3_step(Ud, dt=dt, status=status)
+    assert int(status.item()) & 1
+
+
+def test_autotune_keeps_results_and_picks_a_candidate(lib, ora, W):
+    prob, U, _ = W.riemann2d(seed=0, n=96)
+    say("autotune")
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0)
+    Ud = to_dev(U)
+    tiles = G.autotune(Ud)
+    assert tiles[0] in (64, 128, 256) and tiles[1] in (16, 32, 64) and tiles[2] in (64, 128, 256)
+    _check(to_host(G.residual(Ud)), O.residual(U), what="after autotune")
