@@ -1,0 +1,246 @@
+#!/usr/bin/env python
+"""Throughput of the WCNS-FE residual + SSP-RK3 step on one MI355X.
+
+Workload: a batch of 4096 independent 1D Euler shock tubes (gamma = 1.4),
+N_p uniform in [256, 4096] (seed 0: 8.97 M points in total), left/right
+(rho, u, p) drawn from the seed, transmissive ends, FE weights (xi = 100,
+kappa = 0.5, p = 2, eps = 1e-40), characteristic projection, MND6, SSP-RK3
+at CFL 0.5 with a per-problem dt.  One "step" is one graph-replayed SSP-RK3
+step of every problem (per-problem CFL kernel + three persistent stage
+kernels); states are resident in HBM before timing starts.
+
+Prints one JSON line with the metric (grid-point RK3-stage updates per
+second), the roofline of the dominant kernel (the batch stage kernel) and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X FP64 vector (published)
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E (published)
+T_END = 0.2
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--weights", default="fe")
+    ap.add_argument("--xi", type=float, default=100.0)
+    ap.add_argument("--no-graph", action="store_true", help="launch the step eagerly")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def algorithmic_flops_per_point_stage(ora, prob_kw, U_small, n_small):
+    """Arithmetic of one residual per node from the oracle's operation tally
+    (each +, -, x, /, sqrt and tanh counts as one flop), plus the stage
+    combine (5 per variable)."""
+    P = ora.Problem(**prob_kw, n=(n_small,), h=(1.0 / (n_small - 1),))
+    c = P.count_residual_ops(U_small)
+    return sum(c.values()) / n_small + 5 * 3, c
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the residual path has no multi-GPU form in this "
+              "library (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2306_09760_amd import workloads as W
+    from paper_2306_09760_amd.solver import BatchPlan, Plan
+
+    dev = torch.device("cuda")
+    proto = dict(weights=args.weights, xi=args.xi, kappa=0.5, zpow=2, eps=1e-40, diff="mnd6",
+                 charproj=True, gamma=1.4, bc="transmissive")
+    prob, U_host, meta = W.shock_tube_batch(seed=args.seed)
+    lengths = meta["lengths"].astype(np.int64)
+    B = BatchPlan(meta["offsets"], meta["h"], **proto)
+    U0 = torch.from_numpy(U_host).to(dev)
+    U = U0.clone()
+    tile = B.autotune(U)
+    B.set_graph(not args.no_graph)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def reset(t):
+        U.copy_(U0)
+        t.zero_()
+
+    t = torch.zeros(B.nprob, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        B.rk3_step(U, t, T_END, 0.5, status)
+    reset(t)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K graph-replayed steps ----------------------------
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        B.rk3_step(U, t, T_END, 0.5, status)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1)
+    bad = int(status.item())
+
+    # Active points per step (problems stop at t = 0.2): replay untimed with a
+    # snapshot of t before every step.
+    reset(t)
+    active_pts = 0
+    for _ in range(args.steps):
+        active = (t < T_END).cpu().numpy()
+        active_pts += int(lengths[active].sum())
+        B.rk3_step(U, t, T_END, 0.5, status)
+    torch.cuda.synchronize()
+    pt_stages = 3 * active_pts
+    value = pt_stages / (ms * 1e-3)
+
+    # ---- dominant kernel: the persistent batch stage kernel ---------------
+    reset(t)
+    B.cfl(U, t, T_END, 0.5)
+    out = torch.empty_like(U)
+    nk = max(args.steps, 10)
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    B.stage(2, U, U, out)  # warm
+    k0.record()
+    for _ in range(nk):
+        B.stage(2, U, U, out)
+    k1.record()
+    torch.cuda.synchronize()
+    kernel_ms = k0.elapsed_time(k1) / nk
+    total_pts = int(lengths.sum())
+
+    import oracle
+    small = W.shock_tube(1.0, 0.75, 1.0, 0.125, 0.0, 0.1, 512)
+    okw = {k: v for k, v in proto.items()}
+    flops_pt, counts = algorithmic_flops_per_point_stage(
+        oracle, dict(system="euler", ndim=1, **okw), small[1], 512)
+    kernel_flops = flops_pt * total_pts
+    achieved_tflops = kernel_flops / (kernel_ms * 1e-3) / 1e12
+    bytes_pt = 3 * 3 * 8  # stage 2/3 reads U^(k) and U^n, writes U^(k+1)
+    hbm_gbs = bytes_pt * total_pts / (kernel_ms * 1e-3) / 1e9
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # ---- adjoint / forward step time on the 2D periodic problem ----------
+    adjoint = None
+    if not args.no_adjoint:
+        prob5, U5, _ = W.adjoint2d(seed=args.seed, n=1024)
+        P5 = Plan(**prob5, weights=args.weights, xi=args.xi)
+        U5d = torch.from_numpy(U5).to(dev)
+        P5.autotune(U5d)
+        dt5 = P5.cfl_dt(U5d, 0.5).clone()
+        lam = torch.ones_like(U5d)
+        Uf = U5d.clone()
+        P5.rk3_step(Uf, dt=dt5)
+        P5.rk3_step_adjoint(U5d, lam, dt5)
+        torch.cuda.synchronize()
+        reps = 5
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(reps):
+            P5.rk3_step(Uf, dt=dt5)
+        a1.record()
+        torch.cuda.synchronize()
+        fwd_ms = a0.elapsed_time(a1) / reps
+        a0.record()
+        for _ in range(reps):
+            P5.rk3_step_adjoint(U5d, lam, dt5)
+        a1.record()
+        torch.cuda.synchronize()
+        adj_ms = a0.elapsed_time(a1) / reps
+        adjoint = {"workload": "2D Euler periodic 1024^2, smooth density, FE xi=%g" % args.xi,
+                   "forward_step_ms": round(fwd_ms, 4), "adjoint_step_ms": round(adj_ms, 4),
+                   "ratio": round(adj_ms / fwd_ms, 3),
+                   "note": "adjoint step includes recomputing the two stage states"}
+
+    # ---- CPU oracle on a bounded sample ----------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        sample = np.arange(0, B.nprob, 3)
+        o = meta["offsets"]
+        t0 = time.perf_counter()
+        npts = 0
+        for p in sample:
+            P = oracle.Problem(system="euler", ndim=1, n=(int(lengths[p]),), h=(meta["h"][p],),
+                               **okw)
+            Up = U_host[:, o[p]:o[p + 1]]
+            dtp = P.cfl_dt(Up, 0.5)
+            P.rk3_step(Up, dtp)
+            npts += int(lengths[p])
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": 3 * npts / cpu_s, "unit": "grid-point RK3-stage updates/s", "cores": 1,
+               "kind": "oracle",
+               "sample": "one SSP-RK3 step of every third problem of the batch "
+                         f"({len(sample)} problems, {npts} points, {cpu_s:.1f} s, single thread)"}
+
+    line = {
+        "metric": "grid-point RK3-stage updates/s (FP64), % HBM roofline; adjoint/forward time ratio",
+        "value": value,
+        "unit": "grid-point RK3-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "batch of 4096 independent 1D Euler shock tubes, N_p uniform in "
+                        "[256,4096], FE weights, MND6, SSP-RK3 CFL 0.5, per-problem dt",
+            "nprob": int(B.nprob), "total_points": total_pts, "seed": args.seed,
+            "weights": args.weights, "xi": args.xi, "tile_midpoints": int(tile),
+            "graph": not args.no_graph, "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "kernel": "xsweep_kernel<3, stage, batch>",
+            "kernel_ms": kernel_ms,
+            "flops_per_point_stage": flops_pt,
+            "hbm_algorithmic_gbs": hbm_gbs,
+            "hbm_frac": hbm_gbs / PEAK_HBM_GBS,
+        },
+        "cpu_baseline": cpu,
+        "adjoint_forward": adjoint,
+        "status_word": bad,
+        "wall_s": wall,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,7 +150,8 @@ wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]);
    offsets_host[p+1] - offsets_host[p] >= 9 nodes at columns
    offsets_host[p] .. offsets_host[p+1]-1 of every variable of the batch
    state U[v*total + column], total = offsets_host[nprob]; its spacing is
-   h_host[p].  The library copies offsets and h (synchronously). */
+   h_host[p].  The library copies offsets and h to small device tables of
+   its own (synchronously; freed by wcns_batch_plan_destroy). */
 wcns_status wcns_batch_plan_create(const wcns_desc* proto, int64_t nprob,
                                    const int64_t* offsets_host, const double* h_host,
                                    wcns_batch_plan** plan);
@@ -171,6 +172,19 @@ wcns_status wcns_batch_residual(wcns_batch_plan* plan, const double* U, double* 
 wcns_status wcns_batch_rk3_step(wcns_batch_plan* plan, double* U, void* work, double* t_dev,
                                 double t_end, double cfl, int32_t* status_dev, void* stream);
 wcns_status wcns_batch_set_graph(wcns_batch_plan* plan, int32_t enable);
+
+/* The two kernels of wcns_batch_rk3_step, for callers composing their own
+   step.  wcns_batch_cfl: per-problem dt_p (as above) into the workspace and
+   t_dev[p] += dt_p.  wcns_batch_stage: SSP-RK3 stage `stage` (1, 2 or 3) of
+   every problem with dt_p > 0, out = a*U0 + b*(Uk + dt_p*L(Uk)) with
+   (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3); Uk, U0 and out are batch states,
+   out may alias U0 but not Uk.  dt_p is the one the last wcns_batch_cfl
+   (or wcns_batch_rk3_step) left in `work`. */
+wcns_status wcns_batch_cfl(wcns_batch_plan* plan, const double* U, void* work, double* t_dev,
+                           double t_end, double cfl, void* stream);
+wcns_status wcns_batch_stage(wcns_batch_plan* plan, int32_t stage, const double* Uk,
+                             const double* U0, double* out, void* work, int32_t* status_dev,
+                             void* stream);
 /* Candidate midpoints-per-tile are timed on U as in wcns_plan_autotune. */
 wcns_status wcns_batch_autotune(wcns_batch_plan* plan, const double* U, void* work,
                                 void* stream);

@@ -18,6 +18,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wcns_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The same source built with fused multiply-add contraction: a second, equally
+# valid rounding of the same arithmetic, used to measure how sensitive a long
+# run is to rounding order.
+_LIB_FMA = os.path.join(_HERE, "liboracle_fma.so")
 
 SYSTEMS = {"advection": 0, "euler": 1}
 BCS = {"periodic": 0, "transmissive": 1}
@@ -26,13 +30,14 @@ DIFFS = {"mnd6": 0, "md6": 1}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (no FMA contraction) into liboracle.so."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call([
-            "g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
-            "-o", tmp, _SRC])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with g++ into liboracle.so (no FMA contraction) and
+    liboracle_fma.so (FMA contraction)."""
+    for path, fp in ((_LIB, ["-ffp-contract=off"]), (_LIB_FMA, ["-mfma", "-ffp-contract=fast"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["g++", "-O2", "-std=c++17", *fp, "-fPIC", "-shared",
+                                   "-o", tmp, _SRC])
+            os.replace(tmp, path)
     return _LIB
 
 
@@ -47,15 +52,15 @@ class _Desc(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
-        L = C.CDLL(_LIB)
+def lib(variant: str = "plain"):
+    if variant not in _libs:
+        path = {"plain": _LIB, "fma": _LIB_FMA}[variant]
+        if not os.path.exists(path):
+            build(force=False)
+        L = C.CDLL(path)
         P = C.POINTER(C.c_double)
         D = C.POINTER(_Desc)
         L.ora_nvars.argtypes = [D]
@@ -79,8 +84,8 @@ def lib():
         L.ora_euler_flux.argtypes = [C.c_int, C.c_int, C.c_double, P, P]
         L.ora_midpoint_flux.argtypes = [D, C.c_int, P, P]
         L.ora_count_residual_ops.argtypes = [D, P, C.POINTER(C.c_longlong)]
-        _lib = L
-    return _lib
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _p(a: np.ndarray):
@@ -95,7 +100,7 @@ class Problem:
     def __init__(self, *, system="euler", ndim=1, n=(16,), h=None, gamma=1.4,
                  adv=(1.0, 1.0, 1.0), bc="periodic", weights="fe", zpow=2,
                  diff="mnd6", charproj=True, eps=1e-40, xi=1e6, kappa=0.5,
-                 cv=1e-3):
+                 cv=1e-3, variant="plain"):
         n = tuple(int(v) for v in n)
         assert len(n) == ndim
         if h is None:
@@ -116,6 +121,7 @@ class Problem:
         d.diff = DIFFS[diff]
         d.charproj = 1 if charproj else 0
         self.desc = d
+        self.variant = variant
         self.ndim, self.n, self.h = ndim, n, h
         self.nv = 1 if system == "advection" else ndim + 2
         self.npts = int(np.prod(n))
@@ -135,7 +141,7 @@ class Problem:
     def residual(self, U):
         U = self._u(U)
         R = np.empty_like(U)
-        lib().ora_residual(self._ref(), _p(U), _p(R))
+        lib(self.variant).ora_residual(self._ref(), _p(U), _p(R))
         return R
 
     def residual_jvp(self, U, V):
@@ -143,38 +149,38 @@ class Problem:
         V = self._u(V)
         R = np.empty_like(U)
         JV = np.empty_like(U)
-        lib().ora_residual_jvp(self._ref(), _p(U), _p(V), _p(R), _p(JV))
+        lib(self.variant).ora_residual_jvp(self._ref(), _p(U), _p(V), _p(R), _p(JV))
         return R, JV
 
     def cfl_dt(self, U, cfl):
         U = self._u(U)
-        return lib().ora_cfl_dt(self._ref(), _p(U), cfl)
+        return lib(self.variant).ora_cfl_dt(self._ref(), _p(U), cfl)
 
     def check_state(self, U):
         U = self._u(U)
-        return lib().ora_check_state(self._ref(), _p(U))
+        return lib(self.variant).ora_check_state(self._ref(), _p(U))
 
     def rk3_step(self, U, dt):
         U = self._u(U).copy()
-        bad = lib().ora_rk3_step(self._ref(), _p(U), dt)
+        bad = lib(self.variant).ora_rk3_step(self._ref(), _p(U), dt)
         return U, bad
 
     def rk3_step_jvp(self, U, V, dt):
         U = self._u(U).copy()
         V = self._u(V).copy()
-        bad = lib().ora_rk3_step_jvp(self._ref(), _p(U), _p(V), dt)
+        bad = lib(self.variant).ora_rk3_step_jvp(self._ref(), _p(U), _p(V), dt)
         return U, V, bad
 
     def run_steps(self, U, nsteps, cfl=0.5, dt=0.0):
         U = self._u(U).copy()
-        bad = lib().ora_run_steps(self._ref(), _p(U), cfl, dt, int(nsteps))
+        bad = lib(self.variant).ora_run_steps(self._ref(), _p(U), cfl, dt, int(nsteps))
         return U, bad
 
     def run_to_time(self, U, t_end, cfl=0.5, max_steps=10**9):
         U = self._u(U).copy()
         s = C.c_int64(0)
         t = C.c_double(0.0)
-        bad = lib().ora_run_to_time(self._ref(), _p(U), cfl, t_end, max_steps,
+        bad = lib(self.variant).ora_run_to_time(self._ref(), _p(U), cfl, t_end, max_steps,
                                     C.byref(s), C.byref(t))
         return U, s.value, t.value, bad
 
@@ -182,27 +188,27 @@ class Problem:
         u5 = np.ascontiguousarray(u5, dtype=np.float64)
         wb = np.empty(3)
         wo = np.empty(3)
-        v = lib().ora_interpolate(self._ref(), _p(u5), _p(wb), _p(wo))
+        v = lib(self.variant).ora_interpolate(self._ref(), _p(u5), _p(wb), _p(wo))
         return v, wb, wo
 
     def interpolate_jvp(self, u5, du5):
         u5 = np.ascontiguousarray(u5, dtype=np.float64)
         du5 = np.ascontiguousarray(du5, dtype=np.float64)
         d = C.c_double(0.0)
-        v = lib().ora_interpolate_jvp(self._ref(), _p(u5), _p(du5), C.byref(d))
+        v = lib(self.variant).ora_interpolate_jvp(self._ref(), _p(u5), _p(du5), C.byref(d))
         return v, d.value
 
     def midpoint_flux(self, nodes, d=0):
         nodes = np.ascontiguousarray(nodes, dtype=np.float64)
         assert nodes.shape == (6, self.nv)
         F = np.empty(self.nv)
-        lib().ora_midpoint_flux(self._ref(), d, _p(nodes), _p(F))
+        lib(self.variant).ora_midpoint_flux(self._ref(), d, _p(nodes), _p(F))
         return F
 
     def count_residual_ops(self, U):
         U = self._u(U)
         c = (C.c_longlong * 5)()
-        lib().ora_count_residual_ops(self._ref(), _p(U), c)
+        lib(self.variant).ora_count_residual_ops(self._ref(), _p(U), c)
         return dict(zip(("add", "mul", "div", "sqrt", "tanh"), list(c)))
 
 

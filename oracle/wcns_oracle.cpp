@@ -189,14 +189,21 @@ T fe_map(int i, T w, double xi, double kappa) {
 // actually used.
 template <class T>
 T interpolate(const Desc& D, const T u[5], T* w_base = nullptr, T* w_out = nullptr) {
-  // Smoothness indicators, eq. 9-10 (the powers of h cancel).
+  // Smoothness indicators, eq. 9-10 (the powers of h cancel).  The one-sided
+  // first and second differences of eq. 10 are evaluated through the first
+  // differences du_j = u_{j+1} - u_j of the stencil, e.g.
+  //   u_{i-2} - 4u_{i-1} + 3u_i = 3 du_{i-1} - du_{i-2},
+  // which is the same polynomial in u but makes a sub-stencil of equal values
+  // give IS = 0 exactly, whatever the rounding of the products.
+  T du[4];
+  for (int j = 0; j < 4; ++j) du[j] = u[j + 1] - u[j];
   T hf[3], hs[3], IS[3];
-  hf[0] = T(0.5) * (u[0] - T(4.0) * u[1] + T(3.0) * u[2]);
-  hs[0] = u[0] - T(2.0) * u[1] + u[2];
-  hf[1] = T(0.5) * (u[3] - u[1]);
-  hs[1] = u[1] - T(2.0) * u[2] + u[3];
-  hf[2] = T(0.5) * (T(-3.0) * u[2] + T(4.0) * u[3] - u[4]);
-  hs[2] = u[2] - T(2.0) * u[3] + u[4];
+  hf[0] = T(0.5) * (T(3.0) * du[1] - du[0]);   // (u_{i-2} - 4u_{i-1} + 3u_i) / 2
+  hs[0] = du[1] - du[0];                       //  u_{i-2} - 2u_{i-1} + u_i
+  hf[1] = T(0.5) * (du[1] + du[2]);            // (u_{i+1} - u_{i-1}) / 2
+  hs[1] = du[2] - du[1];                       //  u_{i-1} - 2u_i + u_{i+1}
+  hf[2] = T(0.5) * (T(3.0) * du[2] - du[3]);   // (-3u_i + 4u_{i+1} - u_{i+2}) / 2
+  hs[2] = du[3] - du[2];                       //  u_i - 2u_{i+1} + u_{i+2}
   for (int k = 0; k < 3; ++k) IS[k] = hf[k] * hf[k] + hs[k] * hs[k];
 
   T w[3];

@@ -29,7 +29,7 @@ EXPORTS = [
     "wcns_batch_plan_destroy", "wcns_batch_state_elems", "wcns_batch_workspace_bytes",
     "wcns_batch_residual", "wcns_batch_rk3_step", "wcns_batch_set_graph",
     "wcns_batch_autotune", "wcns_batch_get_tile", "wcns_batch_set_tile",
-    "wcns_status_string", "wcns_last_error",
+    "wcns_batch_cfl", "wcns_batch_stage", "wcns_status_string", "wcns_last_error",
 ]
 
 
@@ -84,6 +84,8 @@ def lib():
         "wcns_batch_residual": (st, [vp, vp, vp, vp, vp]),
         "wcns_batch_rk3_step": (st, [vp, vp, vp, vp, C.c_double, C.c_double, vp, vp]),
         "wcns_batch_set_graph": (st, [vp, C.c_int32]),
+        "wcns_batch_cfl": (st, [vp, vp, vp, vp, C.c_double, C.c_double, vp]),
+        "wcns_batch_stage": (st, [vp, C.c_int32, vp, vp, vp, vp, vp, vp]),
         "wcns_batch_autotune": (st, [vp, vp, vp, vp]),
         "wcns_batch_get_tile": (C.c_int32, [vp]),
         "wcns_batch_set_tile": (st, [vp, C.c_int32]),

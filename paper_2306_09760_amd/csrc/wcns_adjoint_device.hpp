@@ -56,9 +56,10 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     c1b = D1 * yb;
     c2b = D2 * yb;
   } else {
-    const double f0 = 0.5 * (a - 4.0 * b + 3.0 * c), s0 = a - 2.0 * b + c;
-    const double f1 = 0.5 * (e - b), s1 = b - 2.0 * c + e;
-    const double f2 = 0.5 * (-3.0 * c + 4.0 * e - f), s2 = c - 2.0 * e + f;
+    const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
+    const double f0 = 0.5 * (3.0 * d1 - d0), s0 = d1 - d0;
+    const double f1 = 0.5 * (d1 + d2), s1 = d2 - d1;
+    const double f2 = 0.5 * (3.0 * d2 - d3), s2 = d3 - d2;
     const double IS0 = f0 * f0 + s0 * s0;
     const double IS1 = f1 * f1 + s1 * s1;
     const double IS2 = f2 * f2 + s2 * s2;
@@ -149,11 +150,16 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     const double f0b = 2.0 * f0 * ISb0, s0b = 2.0 * s0 * ISb0;
     const double f1b = 2.0 * f1 * ISb1, s1b = 2.0 * s1 * ISb1;
     const double f2b = 2.0 * f2 * ISb2, s2b = 2.0 * s2 * ISb2;
-    ab += 0.5 * f0b + s0b;
-    bb += -2.0 * f0b - 2.0 * s0b - 0.5 * f1b + s1b;
-    cb += 1.5 * f0b + s0b - 2.0 * s1b - 1.5 * f2b + s2b;
-    eb += 0.5 * f1b + s1b + 2.0 * f2b - 2.0 * s2b;
-    fb += -0.5 * f2b + s2b;
+    // back through the first differences d0..d3
+    const double db0 = -0.5 * f0b - s0b;
+    const double db1 = 1.5 * f0b + s0b + 0.5 * f1b - s1b;
+    const double db2 = 0.5 * f1b + s1b + 1.5 * f2b - s2b;
+    const double db3 = -0.5 * f2b + s2b;
+    ab -= db0;
+    bb += db0 - db1;
+    cb += db1 - db2;
+    eb += db2 - db3;
+    fb += db3;
   }
   ab += 0.375 * c0b;
   bb += -1.25 * c0b - 0.125 * c1b;

@@ -716,6 +716,42 @@ wcns_status wcns_batch_rk3_step(wcns_batch_plan* B, double* U, void* work, doubl
   return WCNS_OK;
 }
 
+wcns_status wcns_batch_cfl(wcns_batch_plan* B, const double* U, void* work, double* t_dev,
+                           double t_end, double cfl, void* stream) {
+  g_err.clear();
+  if (!B || !U || !work || !t_dev) return fail(WCNS_EINVAL, "NULL argument");
+  if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0");
+  if (!std::isfinite(t_end)) return fail(WCNS_EINVAL, "t_end must be finite");
+  SweepArgs a;
+  BatchArgs b;
+  batch_args(B, (double*)((char*)work + B->off_dtp), &a, &b);
+  WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl, (hipStream_t)stream),
+           "batch cfl launch");
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_stage(wcns_batch_plan* B, int32_t stage, const double* Uk, const double* U0,
+                             double* out, void* work, int32_t* status_dev, void* stream) {
+  g_err.clear();
+  if (!B || !Uk || !U0 || !out || !work) return fail(WCNS_EINVAL, "NULL argument");
+  if (stage < 1 || stage > 3) return fail(WCNS_EINVAL, "stage %d not in 1..3", stage);
+  if (out == Uk) return fail(WCNS_EINVAL, "out must not alias Uk");
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  SweepArgs a;
+  BatchArgs b;
+  batch_args(B, (double*)((char*)work + B->off_dtp), &a, &b);
+  a.status = status_dev;
+  a.U = Uk;
+  a.U0 = U0;
+  a.out = out;
+  a.ca = ca[stage - 1];
+  a.cb = cb[stage - 1];
+  WCNS_HIP(launch_batch_xsweep(a, b, MODE_STAGE, B->tm, B->grid, (hipStream_t)stream),
+           "batch stage launch");
+  return WCNS_OK;
+}
+
 wcns_status wcns_batch_set_graph(wcns_batch_plan* B, int32_t enable) {
   g_err.clear();
   if (!B) return fail(WCNS_EINVAL, "NULL plan");

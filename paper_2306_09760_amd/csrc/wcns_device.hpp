@@ -112,10 +112,16 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
   const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
   if (P.weights == WLIN) return D0 * c0 + D1 * c1 + D2 * c2;
 
-  // Smoothness indicators, eq. 9-10.
-  const double f0 = 0.5 * (a - 4.0 * b + 3.0 * c), s0 = a - 2.0 * b + c;
-  const double f1 = 0.5 * (e - b), s1 = b - 2.0 * c + e;
-  const double f2 = 0.5 * (-3.0 * c + 4.0 * e - f), s2 = c - 2.0 * e + f;
+  // Smoothness indicators, eq. 9-10, written through the first differences of
+  // the stencil so that a sub-stencil of equal values gives IS = 0 exactly
+  // (with FMA contraction too).  At steepness xi ~ 100 the FE map keeps a
+  // small weight g_0(0) on a stencil across a jump, and how that weight is
+  // renormalised depends on the ratio of the two flat stencils' weights, so
+  // flat stencils must not see rounding noise.
+  const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
+  const double f0 = 0.5 * (3.0 * d1 - d0), s0 = d1 - d0;
+  const double f1 = 0.5 * (d1 + d2), s1 = d2 - d1;
+  const double f2 = 0.5 * (3.0 * d2 - d3), s2 = d3 - d2;
   const double IS0 = f0 * f0 + s0 * s0;
   const double IS1 = f1 * f1 + s1 * s1;
   const double IS2 = f2 * f2 + s2 * s2;

@@ -26,7 +26,12 @@ def _stream():
 def _require_device(device):
     if not torch.cuda.is_available():
         raise _lib.WCNSError("no HIP device is visible: the WCNS library runs on the GPU only")
-    return torch.device(device)
+    d = torch.device(device)
+    if d.type != "cuda":
+        raise _lib.WCNSError(f"device {d} is not a HIP device")
+    if d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
 
 
 class Plan:
@@ -170,6 +175,20 @@ class BatchPlan:
         check(lib().wcns_batch_rk3_step(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
                                         float(cfl), _ptr(status), _stream()), "wcns_batch_rk3_step")
         return U
+
+    def cfl(self, U, t, t_end, cfl=0.5):
+        """Per-problem dt into the workspace; t += dt (first kernel of a step)."""
+        self._check_state(U)
+        check(lib().wcns_batch_cfl(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
+                                   float(cfl), _stream()), "wcns_batch_cfl")
+
+    def stage(self, stage, Uk, U0, out, status=None):
+        """One SSP-RK3 stage with the dt of the last cfl()/rk3_step()."""
+        for x in (Uk, U0, out):
+            self._check_state(x)
+        check(lib().wcns_batch_stage(self._h, int(stage), _ptr(Uk), _ptr(U0), _ptr(out),
+                                     _ptr(self.work), _ptr(status), _stream()), "wcns_batch_stage")
+        return out
 
     def set_graph(self, enable=True):
         check(lib().wcns_batch_set_graph(self._h, 1 if enable else 0), "wcns_batch_set_graph")

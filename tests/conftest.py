@@ -18,8 +18,8 @@ def ora():
     """The CPU oracle (built with g++ if its shared object is missing)."""
     import oracle
     from oracle import oracle as _o
-    if not os.path.exists(_o._LIB):
-        oracle.build(force=True)
+    if not (os.path.exists(_o._LIB) and os.path.exists(_o._LIB_FMA)):
+        oracle.build(force=False)
     return oracle
 
 

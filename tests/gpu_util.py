@@ -34,3 +34,16 @@ def say(*a):
     """Names the case on stdout before GPU work (flushed)."""
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+RUN_TOL = 1e-9
+
+
+def run_tolerance(ref, alt):
+    """Bar for a multi-step run: 1e-9 normwise, unless the method itself is
+    more sensitive to rounding order on this input.  ``alt`` is the same run
+    of the oracle built with FMA contraction (another valid rounding of the
+    same arithmetic); the GPU may differ from the oracle by up to ten times
+    that spread.  Returns (normwise bar, pointwise bar, spread)."""
+    n, p = rel_err(alt, ref)
+    return max(RUN_TOL, 10 * n), max(RUN_TOL, 10 * p), (n, p)

@@ -108,7 +108,7 @@ def test_adjoint_matches_central_differences_of_gpu_forward(lib, W):
     Ud = to_dev(U)
     Ub = to_host(G.residual_adjoint(Ud, to_dev(Rb)))
     best = np.inf
-    for eps in (1e-5, 1e-6, 1e-7):
+    for eps in (1e-5, 1e-6, 1e-7, 1e-8):
         Rp = to_host(G.residual(to_dev(U + eps * V)))
         Rm = to_host(G.residual(to_dev(U - eps * V)))
         fd = float(np.sum(Rb * (Rp - Rm))) / (2 * eps)

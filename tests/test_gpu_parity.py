@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import rel_err, say, to_dev, to_host
+from gpu_util import rel_err, run_tolerance, say, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -18,6 +18,9 @@ POINT_TOL = 1e-10
 RUN_TOL = 1e-9
 
 WEIGHTS = [("js", 100.0), ("z", 100.0), ("fe", 100.0), ("fe", 1e6), ("pfe", 100.0), ("linear", 100.0)]
+# The unlimited linear scheme (ideal weights) is not defined on shock data:
+# its interpolated states reach negative pressure (NaN on both sides).
+SHOCK_WEIGHTS = [w for w in WEIGHTS if w[0] != "linear"]
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +49,7 @@ def test_residual_advection_config1(lib, ora, W, weights, xi, diff):
     _check(to_host(G.residual(to_dev(U))), O.residual(U), what="advection")
 
 
-@pytest.mark.parametrize("weights,xi", WEIGHTS)
+@pytest.mark.parametrize("weights,xi", SHOCK_WEIGHTS)
 @pytest.mark.parametrize("bc", ["transmissive", "periodic"])
 @pytest.mark.parametrize("charproj", [True, False])
 def test_residual_euler1d(lib, ora, W, weights, xi, bc, charproj):
@@ -72,7 +75,7 @@ def test_xsweep_tile_shape_invariance(lib, W, tm, diff):
 
 
 # ------------------------------------------------------------------------ 2D --
-@pytest.mark.parametrize("weights,xi", WEIGHTS)
+@pytest.mark.parametrize("weights,xi", SHOCK_WEIGHTS)
 @pytest.mark.parametrize("diff", ["mnd6", "md6"])
 def test_residual_riemann2d(lib, ora, W, weights, xi, diff):
     prob, U, _ = W.riemann2d(seed=0, n=70)
@@ -176,7 +179,10 @@ def test_riemann2d_multi_step_run(lib, ora, W):
     for _ in range(20):
         G.rk3_step(Ud, cfl=0.5)
     Uo, bad = O.run_steps(U, 20, cfl=0.5)
-    _check(to_host(Ud), Uo, tol=RUN_TOL, ptol=RUN_TOL, what="riemann2d run")
+    Uf, _ = ora.Problem(**prob, weights="fe", xi=100.0, variant="fma").run_steps(U, 20, cfl=0.5)
+    tol, ptol, spread = run_tolerance(Uo, Uf)
+    say("oracle rounding-order spread", spread)
+    _check(to_host(Ud), Uo, tol=tol, ptol=ptol, what="riemann2d run")
 
 
 def test_status_word_flags_nonphysical_state(lib, W):
