@@ -12,7 +12,8 @@ import os
 import torch  # noqa: F401  (load PyTorch's HIP runtime before the library)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libwcns.so")
+# The in-tree build; WCNS_LIB may name another build of the same library.
+LIB_PATH = os.environ.get("WCNS_LIB") or os.path.join(HERE, "libwcns.so")
 
 WCNS_OK, WCNS_EINVAL, WCNS_ENOMEM, WCNS_EDEVICE, WCNS_ENONPHYS, WCNS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SYSTEMS = {"advection": 0, "euler": 1}

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libwcns.so")
-SOURCES = ["wcns_api.hip", "wcns_kernels.hip", "wcns_adjoint.hip"]
+SOURCES = ["wcns_api.hip", "wcns_kernels.hip", "wcns_march.hip", "wcns_adjoint.hip"]
 ARCH = os.environ.get("WCNS_OFFLOAD_ARCH", "gfx950")
 
 
@@ -24,7 +24,8 @@ def hipcc() -> str:
 
 
 def flags():
-    return [
+    extra = os.environ.get("WCNS_HIPCC_FLAGS", "").split()
+    return [*extra,
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         # packed FP32 instructions stay off (the path is FP64 anyway)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -41,20 +42,21 @@ def _compile(src: str, obj_dir: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str | None = None) -> str:
     obj_dir = os.path.join(HERE, "_build")
     os.makedirs(obj_dir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, obj_dir), SOURCES))
-    tmp = LIB + ".tmp"
+    target = out or LIB
+    tmp = target + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, target)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", target)
+    return target
 
 
 if __name__ == "__main__":

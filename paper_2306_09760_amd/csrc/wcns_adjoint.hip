@@ -44,7 +44,7 @@ __device__ __forceinline__ double rbar_at(const double* Rb, int64_t base, int64_
   return Rb[base + j * stride];
 }
 
-template <int NV, int DIR>
+template <int NV, int DIR, int SPEC>
 __global__ void __launch_bounds__(256) adj_midpoint_kernel(AdjArgs a, AdjGeom g) {
   const int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (lin >= g.Mtot) return;
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) adj_midpoint_kernel(AdjArgs a, AdjGeom g)
       sb[k][v] = 0.0;
     }
   }
-  midpoint_flux_vjp<NV, DIR>(a.ip, a.pp, s, Fb, sb);
+  midpoint_flux_vjp<NV, DIR, SPEC>(a.ip, a.pp, s, Fb, sb);
 #pragma unroll
   for (int k = 0; k < 6; ++k)
 #pragma unroll
@@ -184,7 +184,12 @@ template <int NV, int DIR>
 static hipError_t adj_go(const AdjArgs& a, hipStream_t s) {
   const AdjGeom g = make_geom(DIR, a.n, a.diff, a.bc);
   const int64_t b1 = (g.Mtot + 255) / 256;
-  hipLaunchKernelGGL((adj_midpoint_kernel<NV, DIR>), dim3((unsigned)b1), dim3(256), 0, s, a, g);
+  if (spec_of(a.ip) == SPEC_FE)
+    hipLaunchKernelGGL((adj_midpoint_kernel<NV, DIR, SPEC_FE>), dim3((unsigned)b1), dim3(256), 0, s,
+                       a, g);
+  else
+    hipLaunchKernelGGL((adj_midpoint_kernel<NV, DIR, SPEC_GENERIC>), dim3((unsigned)b1), dim3(256),
+                       0, s, a, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t b2 = (a.npts + 255) / 256;

@@ -10,48 +10,28 @@
 
 namespace wcns {
 
-// d tanh_sat(x) / dx = 1 - tanh^2 (exactly 0 where tanh_sat saturates).
-__device__ __forceinline__ double dtanh_from(double t) { return 1.0 - t * t; }
-
-// g_i(w) and g_i'(w) of eq. 20 (see fe_g0 .. fe_g2).
+// g_i(w) and g_i'(w) of eq. 20 (see fe_map; d tanh = 1 - tanh^2, exactly 0
+// where tanh saturates to +-1).
+template <int SPEC>
 __device__ __forceinline__ double fe_g_d(int i, double w, const InterpParams& P, double* dg) {
-  // amplitude A_j(w) = cA_j + sA_j * w (sA_j in {-1/2, 0, +1/2})
-  double g = w, d = 1.0;
-  auto term = [&](double cA, double sA, double nu) {
-    const double t = tanh_sat(P.xi * (w - nu));
-    const double A = cA + sA * w;
-    g += A * t;
-    d += sA * t + A * P.xi * dtanh_from(t);
-  };
-  if (i == 0) {
-    term(0.5 * D0, -0.5, P.nu[0]);
-    term(0.5 * (1.0 / 6.0 - D0), 0.0, P.nu[1]);
-    term(-0.5 / 6.0, 0.5, P.nu[2]);
-  } else if (i == 1) {
-    term(0.5 * D1, -0.5, P.nu[3]);
-    term(0.5 * (0.5 - D1), 0.0, P.nu[4]);
-    term(0.5 * (5.0 / 6.0 - 0.5), 0.0, P.nu[5]);
-    term(-0.5 * 5.0 / 6.0, 0.5, P.nu[6]);
-  } else {
-    term(0.5 * D2, -0.5, P.nu[7]);
-    term(0.5 * (0.5 - D2), 0.0, P.nu[8]);
-    term(-0.25, 0.5, P.nu[9]);
-  }
-  *dg = d;
-  return g;
+  if (i == 0) return fe_g0<SPEC>(w, P, dg);
+  if (i == 1) return fe_g1<SPEC>(w, P, dg);
+  return fe_g2<SPEC>(w, P, dg);
 }
 
 // Cotangent of interp5's inputs (a, b, c, e, f) for output cotangent yb;
 // accumulates into the five references.
+template <int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, double b, double c,
                                             double e, double f, double yb, double& ab, double& bb,
                                             double& cb, double& eb, double& fb) {
+  constexpr bool FE = (SPEC == SPEC_FE);
   const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
   const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
   const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
   double w0, w1, w2;
   double c0b, c1b, c2b;
-  if (P.weights == WLIN) {
+  if (!FE && P.weights == WLIN) {
     c0b = D0 * yb;
     c1b = D1 * yb;
     c2b = D2 * yb;
@@ -65,7 +45,9 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     const double IS2 = f2 * f2 + s2 * s2;
     const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
     double a0, a1, a2, tau = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
-    if (P.weights == WJS) {
+    const int zpow = FE ? 2 : P.zpow;
+    const bool js = !FE && P.weights == WJS;
+    if (js) {
       a0 = D0 * r0 * r0;
       a1 = D1 * r1 * r1;
       a2 = D2 * r2 * r2;
@@ -75,7 +57,7 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
       q1 = tau * r1;
       q2 = tau * r2;
       double p0 = q0, p1 = q1, p2 = q2;
-      for (int k = 1; k < P.zpow; ++k) {
+      for (int k = 1; k < zpow; ++k) {
         p0 *= q0;
         p1 *= q1;
         p2 *= q2;
@@ -86,8 +68,8 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     }
     const double inv = rcp(a0 + a1 + a2);
     const double z0 = a0 * inv, z1 = a1 * inv, z2 = a2 * inv;
-    bool map = (P.weights == WFE);
-    if (P.weights == WPFE) {
+    bool map = FE || (P.weights == WFE);
+    if (!FE && P.weights == WPFE) {
       const bool inside = __builtin_fabs(z0 - D0) <= P.cv && __builtin_fabs(z1 - D1) <= P.cv &&
                           __builtin_fabs(z2 - D2) <= P.cv;
       map = !inside;
@@ -95,9 +77,9 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     double zb0, zb1, zb2;
     if (map) {
       double d0, d1, d2;
-      const double g0 = fe_g_d(0, z0, P, &d0);
-      const double g1 = fe_g_d(1, z1, P, &d1);
-      const double g2 = fe_g_d(2, z2, P, &d2);
+      const double g0 = fe_g_d<SPEC>(0, z0, P, &d0);
+      const double g1 = fe_g_d<SPEC>(1, z1, P, &d1);
+      const double g2 = fe_g_d<SPEC>(2, z2, P, &d2);
       const double ginv = rcp(g0 + g1 + g2);
       w0 = g0 * ginv;
       w1 = g1 * ginv;
@@ -122,7 +104,7 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     const double zdot = zb0 * z0 + zb1 * z1 + zb2 * z2;
     const double ab0 = (zb0 - zdot) * inv, ab1 = (zb1 - zdot) * inv, ab2 = (zb2 - zdot) * inv;
     double ISb0, ISb1, ISb2;
-    if (P.weights == WJS) {
+    if (js) {
       // alpha = d r^2, r = 1/(IS + eps): d alpha / d IS = -2 d r^3
       ISb0 = -2.0 * D0 * r0 * r0 * r0 * ab0;
       ISb1 = -2.0 * D1 * r1 * r1 * r1 * ab1;
@@ -130,14 +112,14 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     } else {
       // alpha = d (1 + q^p), q = tau r
       double dp0 = 1.0, dp1 = 1.0, dp2 = 1.0;  // d q^p / dq = p q^(p-1)
-      for (int k = 1; k < P.zpow; ++k) {
+      for (int k = 1; k < zpow; ++k) {
         dp0 *= q0;
         dp1 *= q1;
         dp2 *= q2;
       }
-      const double qb0 = D0 * ab0 * P.zpow * dp0;
-      const double qb1 = D1 * ab1 * P.zpow * dp1;
-      const double qb2 = D2 * ab2 * P.zpow * dp2;
+      const double qb0 = D0 * ab0 * zpow * dp0;
+      const double qb1 = D1 * ab1 * zpow * dp1;
+      const double qb2 = D2 * ab2 * zpow * dp2;
       const double taub = qb0 * r0 + qb1 * r1 + qb2 * r2;
       ISb0 = -qb0 * tau * r0 * r0;
       ISb1 = -qb1 * tau * r1 * r1;
@@ -292,16 +274,16 @@ __device__ __forceinline__ void roe_vjp(const double* UA, const double* UB, doub
 
 // VJP of the midpoint flux: given Fb (NV), accumulate sb[0..5][NV] (must be
 // zeroed by the caller) = (dF/ds)^T Fb.
-template <int NV, int DIR>
+template <int NV, int DIR, int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ void midpoint_flux_vjp(const InterpParams& IP, const PhysParams& PP,
                                                   const double (&s)[6][NV], const double (&Fb)[NV],
                                                   double (&sb)[6][NV]) {
   if constexpr (NV == 1) {
     const double ubL = 0.5 * (PP.adv + __builtin_fabs(PP.adv)) * Fb[0];
     const double ubR = 0.5 * (PP.adv - __builtin_fabs(PP.adv)) * Fb[0];
-    interp5_vjp(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], ubL, sb[0][0], sb[1][0], sb[2][0],
+    interp5_vjp<SPEC>(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], ubL, sb[0][0], sb[1][0], sb[2][0],
                 sb[3][0], sb[4][0]);
-    interp5_vjp(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0], ubR, sb[5][0], sb[4][0], sb[3][0],
+    interp5_vjp<SPEC>(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0], ubR, sb[5][0], sb[4][0], sb[3][0],
                 sb[2][0], sb[1][0]);
   } else {
     constexpr int ND = NV - 2;
@@ -315,16 +297,16 @@ __device__ __forceinline__ void midpoint_flux_vjp(const InterpParams& IP, const 
       for (int j = 0; j < 6; ++j) project<ND, DIR>(r, s[j], W[j]);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        WL[v] = interp5(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
-        WR[v] = interp5(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
+        WL[v] = interp5<SPEC>(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
+        WR[v] = interp5<SPEC>(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
       }
       unproject<ND, DIR>(r, WL, UL);
       unproject<ND, DIR>(r, WR, UR);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        UL[v] = interp5(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
-        UR[v] = interp5(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
+        UL[v] = interp5<SPEC>(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
+        UR[v] = interp5<SPEC>(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
       }
     }
     // LLF
@@ -350,9 +332,9 @@ __device__ __forceinline__ void midpoint_flux_vjp(const InterpParams& IP, const 
     if (!PP.charproj) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        interp5_vjp(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ULb[v], sb[0][v], sb[1][v],
+        interp5_vjp<SPEC>(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ULb[v], sb[0][v], sb[1][v],
                     sb[2][v], sb[3][v], sb[4][v]);
-        interp5_vjp(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v], URb[v], sb[5][v], sb[4][v],
+        interp5_vjp<SPEC>(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v], URb[v], sb[5][v], sb[4][v],
                     sb[3][v], sb[2][v], sb[1][v]);
       }
       return;
@@ -407,9 +389,9 @@ __device__ __forceinline__ void midpoint_flux_vjp(const InterpParams& IP, const 
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      interp5_vjp(IP, Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v], WLb[v], Wb[0][v],
+      interp5_vjp<SPEC>(IP, Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v], WLb[v], Wb[0][v],
                   Wb[1][v], Wb[2][v], Wb[3][v], Wb[4][v]);
-      interp5_vjp(IP, Wst[5][v], Wst[4][v], Wst[3][v], Wst[2][v], Wst[1][v], WRb[v], Wb[5][v],
+      interp5_vjp<SPEC>(IP, Wst[5][v], Wst[4][v], Wst[3][v], Wst[2][v], Wst[1][v], WRb[v], Wb[5][v],
                   Wb[4][v], Wb[3][v], Wb[2][v], Wb[1][v]);
     }
     // Projection W_j = L U_j.

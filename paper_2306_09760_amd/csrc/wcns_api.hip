@@ -46,7 +46,7 @@ wcns_status hip_fail(hipError_t e, const char* what) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-const int kTmCandidates[] = {64, 128, 256};
+const int kTmCandidates[] = {64, 128};
 const int kSegCandidates[] = {16, 32, 64};
 const int kBwCandidates[] = {64, 128, 256};
 
@@ -113,9 +113,31 @@ void interp_params(const wcns_desc* d, InterpParams* ip) {
   ip->eps = d->eps;
   ip->xi = d->xi;
   ip->cv = d->cv;
-  fill_null_points(d->kappa, ip->nu);
+  double nu[10];
+  fill_null_points(d->kappa, nu);
   ip->weights = d->weights;
   ip->zpow = d->z_power;
+  // One exponential per map: reference point c_i = mean of the map's null
+  // points, K_j = exp(2 xi (c_i - nu_j)).  Usable while xi |nu_j - c_i| < 300
+  // (then E = exp(2 xi (w - c_i)) and E K_j stay finite and normal whenever
+  // a term is unsaturated, |xi (w - nu_j)| < 20); otherwise K_j = nu_j and
+  // every unsaturated term takes its own exponential.
+  const int first[3] = {0, 3, 7}, count[3] = {3, 4, 3};
+  double spread = 0.0, c[3];
+  for (int m = 0; m < 3; ++m) {
+    c[m] = 0.0;
+    for (int j = 0; j < count[m]; ++j) c[m] += nu[first[m] + j];
+    c[m] /= count[m];
+    for (int j = 0; j < count[m]; ++j) spread = std::max(spread, std::fabs(c[m] - nu[first[m] + j]));
+  }
+  ip->shared_exp = (d->xi * spread < 300.0) ? 1 : 0;
+  for (int m = 0; m < 3; ++m) {
+    ip->C2[m] = ip->shared_exp ? 2.0 * d->xi * c[m] : 0.0;
+    for (int j = 0; j < count[m]; ++j) {
+      const int k = first[m] + j;
+      ip->K[k] = ip->shared_exp ? std::exp(2.0 * d->xi * (c[m] - nu[k])) : nu[k];
+    }
+  }
 }
 
 int device_cus() {
@@ -161,7 +183,7 @@ struct wcns_batch_plan {
   int32_t* d_tile_prob = nullptr;
   int32_t* d_tile_i0 = nullptr;
   int32_t ntiles = 0;
-  int tm = 256;
+  int tm = 128;
   int grid = 0;
   int cus = 256;
   InterpParams ip;
@@ -278,7 +300,7 @@ wcns_status wcns_plan_create(const wcns_desc* desc, wcns_plan** plan) {
   P->npts = desc->n[0] * desc->n[1] * desc->n[2];
   for (int k = 0; k < 3; ++k) P->ih[k] = k < desc->ndim ? 1.0 / desc->h[k] : 0.0;
   interp_params(desc, &P->ip);
-  P->tm = 256;
+  P->tm = 64;
   P->seg = 32;
   P->bw = 64;
   {
@@ -326,8 +348,8 @@ void wcns_plan_get_tiles(const wcns_plan* plan, int32_t tiles[3]) {
 wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]) {
   g_err.clear();
   if (!plan || !tiles) return fail(WCNS_EINVAL, "NULL argument");
-  if (!in_list(tiles[0], kTmCandidates, 3) || !in_list(tiles[1], kSegCandidates, 3) ||
-      !in_list(tiles[2], kBwCandidates, 3))
+  if (!in_list(tiles[0], kTmCandidates, 2) || tiles[0] > xsweep_max_tm(plan->nv) ||
+      !in_list(tiles[1], kSegCandidates, 3) || !in_list(tiles[2], kBwCandidates, 3))
     return fail(WCNS_EINVAL, "tile shape (%d, %d, %d) not among the candidates", tiles[0], tiles[1],
                 tiles[2]);
   plan->tm = tiles[0];
@@ -480,6 +502,7 @@ wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, voi
   float best = 1e30f;
   int best_tm = plan->tm;
   for (int tm : kTmCandidates) {
+    if (tm > xsweep_max_tm(plan->nv)) continue;
     plan->tm = tm;
     float ms;
     if ((st = time_sweep(0, &ms)) != WCNS_OK) break;
@@ -764,7 +787,8 @@ int32_t wcns_batch_get_tile(const wcns_batch_plan* B) { return B ? B->tm : 0; }
 wcns_status wcns_batch_set_tile(wcns_batch_plan* B, int32_t tile) {
   g_err.clear();
   if (!B) return fail(WCNS_EINVAL, "NULL plan");
-  if (!in_list(tile, kTmCandidates, 3)) return fail(WCNS_EINVAL, "tile %d not among the candidates", tile);
+  if (!in_list(tile, kTmCandidates, 2) || tile > xsweep_max_tm(3))
+    return fail(WCNS_EINVAL, "tile %d not among the candidates", tile);
   if (tile == B->tm) return WCNS_OK;
   B->tm = tile;
   return batch_build_tiles(B);

@@ -34,15 +34,26 @@ namespace wcns {
 // Weight choice codes (same values as wcns_weights in wcns.h).
 enum : int { WJS = 0, WZ = 1, WFE = 2, WPFE = 3, WLIN = 4 };
 
+// Compile-time specialisation of the interpolation.  SPEC_FE is the paper's
+// configuration (FE weights on Z weights with p = 2, one shared exponential
+// per map); SPEC_GENERIC switches on the runtime parameters.
+enum : int { SPEC_GENERIC = 0, SPEC_FE = 1 };
+
 // Uniform parameters of the interpolation, passed by value to kernels.
 struct InterpParams {
   double eps;       // eq. 11 / eq. 14
   double xi;        // steepness of eq. 20
   double cv;        // PFE band (App. A)
-  double nu[10];    // null points kappa*(psi_{i,j} + psi_{i,j-1}):
-                    //   g0: nu[0..2], g1: nu[3..6], g2: nu[7..9]
+  // Per term j of the three maps (g0: 0..2, g1: 3..6, g2: 7..9), with the null
+  // points nu_j = kappa*(psi_{i,j} + psi_{i,j-1}) and a reference point c_i per
+  // map (the mean of its null points):
+  //   shared_exp = 1:  K[j] = exp(2 xi (c_i - nu_j)),  C2[i] = 2 xi c_i
+  //   shared_exp = 0:  K[j] = nu_j                      (C2 unused)
+  double K[10];
+  double C2[3];
   int weights;      // WJS .. WLIN
   int zpow;         // exponent p of eq. 14 (1..4)
+  int shared_exp;   // 1: one exponential per map (xi * max|nu - c| < 300)
 };
 
 // Physics parameters of one sweep.
@@ -61,13 +72,39 @@ __device__ __forceinline__ double rcp(double x) {
   return r;
 }
 
-// tanh(x) = sign(x) * expm1(2|x|) / (expm1(2|x|) + 2).
+// e^z for |z| <= 708 (Cody-Waite reduction z = n ln2 + r, |r| <= ln2/2, then
+// the Taylor polynomial of e^r to degree 13: truncation below 5e-18).
+__device__ __forceinline__ double exp_cw(double z) {
+  constexpr double kLog2e = 0x1.71547652b82fep+0;
+  constexpr double kLn2Hi = 0x1.62e42ff000000p-1;   // ln 2 to 32 bits: n*hi is exact
+  constexpr double kLn2Lo = -0x1.718432a1b0e26p-35; // ln 2 - hi
+  const double n = __builtin_rint(z * kLog2e);
+  double r = __builtin_fma(-n, kLn2Hi, z);
+  r = __builtin_fma(-n, kLn2Lo, r);
+  double p = 1.6059043836821613e-10;            // 1/13!
+  p = __builtin_fma(p, r, 2.08767569878681e-09);  // 1/12!
+  p = __builtin_fma(p, r, 2.505210838544172e-08);
+  p = __builtin_fma(p, r, 2.755731922398589e-07);
+  p = __builtin_fma(p, r, 2.7557319223985893e-06);
+  p = __builtin_fma(p, r, 2.48015873015873e-05);
+  p = __builtin_fma(p, r, 0.0001984126984126984);
+  p = __builtin_fma(p, r, 0.001388888888888889);
+  p = __builtin_fma(p, r, 0.008333333333333333);
+  p = __builtin_fma(p, r, 0.041666666666666664);
+  p = __builtin_fma(p, r, 0.16666666666666666);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p = __builtin_fma(p, r, 1.0);
+  return __builtin_ldexp(p, (int)n);
+}
+
+// tanh(x) = sign(x) (1 - e^{-2|x|}) / (1 + e^{-2|x|}); +-1 for |x| >= 20.
 __device__ __forceinline__ double tanh_sat(double x) {
-  double ax = __builtin_fabs(x);
+  const double ax = __builtin_fabs(x);
   double r = 1.0;
   if (ax < 20.0) {
-    double e = expm1(2.0 * ax);
-    r = e * rcp(e + 2.0);
+    const double e = exp_cw(-2.0 * ax);
+    r = (1.0 - e) * rcp(1.0 + e);
   }
   return __builtin_copysign(r, x);
 }
@@ -75,42 +112,77 @@ __device__ __forceinline__ double tanh_sat(double x) {
 // Ideal weights d_k (Sec. 2).
 constexpr double D0 = 1.0 / 16.0, D1 = 10.0 / 16.0, D2 = 5.0 / 16.0;
 
-// g_i of eq. 20.  phi(i,j) * tanh(xi * phi(i,j) * x) = tanh(xi * x) because
-// tanh is odd and phi = +-1, so the sign table of eq. 21 folds away.  The
-// amplitudes (omega_{i,j} - omega_{i,j-1}) / 2 come from the coefficient
-// table; entries equal to the argument make the amplitude depend on w.
-__device__ __forceinline__ double fe_g0(double w, const InterpParams& P) {
-  double g = w;
-  g += 0.5 * (D0 - w) * tanh_sat(P.xi * (w - P.nu[0]));
-  g += 0.5 * (1.0 / 6.0 - D0) * tanh_sat(P.xi * (w - P.nu[1]));
-  g += 0.5 * (w - 1.0 / 6.0) * tanh_sat(P.xi * (w - P.nu[2]));
+// g_i of eq. 20 for one map with NT terms:
+//   g(w) = w + sum_j A_j(w) tanh(xi (w - nu_j)),  A_j(w) = a_j + b_j w.
+// phi(i,j) * tanh(xi * phi(i,j) * x) = tanh(xi * x) because tanh is odd and
+// phi = +-1, so the sign table of eq. 21 folds away; the amplitudes
+// (omega_{i,j} - omega_{i,j-1}) / 2 come from the coefficient table, and an
+// entry equal to the argument makes b_j = +-1/2.
+// All terms of one map share w, so with E = exp(2 xi w - 2 xi c) every term is
+// tanh(xi (w - nu_j)) = (q_j - 1) / (q_j + 1), q_j = E K_j = exp(2 xi (w -
+// nu_j)): one exponential per map instead of one per term.  A term is
+// saturated (tanh = +-1 in FP64) exactly when q_j is outside (e^-40, e^40).
+// E and E K_j stay finite and normal whenever a term is unsaturated as long
+// as xi |nu_j - c| < 300 (shared_exp); beyond that each unsaturated term
+// takes its own exponential.  If dg is not null it receives g'(w).
+template <int NT, int SPEC>
+__device__ __forceinline__ double fe_map(double w, const double (&a)[NT], const double (&b)[NT],
+                                         const double* K, double C2, const InterpParams& P,
+                                         double* dg) {
+  constexpr double kQlo = 4.248354255291589e-18;  // e^-40
+  constexpr double kQhi = 2.3538526683702e+17;    // e^40
+  const bool shared = (SPEC == SPEC_FE) || P.shared_exp;
+  double g = w, d = 1.0;
+  double E = 0.0;
+  if (shared) E = exp_cw(__builtin_fma(2.0 * P.xi, w, -C2));
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    double t;
+    if (shared) {
+      const double q = E * K[j];
+      t = (q > 1.0) ? 1.0 : -1.0;
+      if (q > kQlo && q < kQhi) t = (q - 1.0) * rcp(q + 1.0);
+    } else {
+      t = tanh_sat(P.xi * (w - K[j]));
+    }
+    const double A = __builtin_fma(b[j], w, a[j]);
+    g = __builtin_fma(A, t, g);
+    if (dg) d += b[j] * t + A * P.xi * (1.0 - t * t);
+  }
+  if (dg) *dg = d;
   return g;
 }
-__device__ __forceinline__ double fe_g1(double w, const InterpParams& P) {
-  double g = w;
-  g += 0.5 * (D1 - w) * tanh_sat(P.xi * (w - P.nu[3]));
-  g += 0.5 * (0.5 - D1) * tanh_sat(P.xi * (w - P.nu[4]));
-  g += 0.5 * (5.0 / 6.0 - 0.5) * tanh_sat(P.xi * (w - P.nu[5]));
-  g += 0.5 * (w - 5.0 / 6.0) * tanh_sat(P.xi * (w - P.nu[6]));
-  return g;
+
+template <int SPEC = SPEC_GENERIC>
+__device__ __forceinline__ double fe_g0(double w, const InterpParams& P, double* dg = nullptr) {
+  constexpr double a[3] = {0.5 * D0, 0.5 * (1.0 / 6.0 - D0), -0.5 / 6.0};
+  constexpr double b[3] = {-0.5, 0.0, 0.5};
+  return fe_map<3, SPEC>(w, a, b, P.K, P.C2[0], P, dg);
 }
-__device__ __forceinline__ double fe_g2(double w, const InterpParams& P) {
-  double g = w;
-  g += 0.5 * (D2 - w) * tanh_sat(P.xi * (w - P.nu[7]));
-  g += 0.5 * (0.5 - D2) * tanh_sat(P.xi * (w - P.nu[8]));
-  g += 0.5 * (w - 0.5) * tanh_sat(P.xi * (w - P.nu[9]));
-  return g;
+template <int SPEC = SPEC_GENERIC>
+__device__ __forceinline__ double fe_g1(double w, const InterpParams& P, double* dg = nullptr) {
+  constexpr double a[4] = {0.5 * D1, 0.5 * (0.5 - D1), 0.5 * (5.0 / 6.0 - 0.5), -0.5 * 5.0 / 6.0};
+  constexpr double b[4] = {-0.5, 0.0, 0.0, 0.5};
+  return fe_map<4, SPEC>(w, a, b, P.K + 3, P.C2[1], P, dg);
+}
+template <int SPEC = SPEC_GENERIC>
+__device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double* dg = nullptr) {
+  constexpr double a[3] = {0.5 * D2, 0.5 * (0.5 - D2), -0.25};
+  constexpr double b[3] = {-0.5, 0.0, 0.5};
+  return fe_map<3, SPEC>(w, a, b, P.K + 7, P.C2[2], P, dg);
 }
 
 // Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
 // u_{i+2}) = (a, b, c, e, f).
+template <int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ double interp5(const InterpParams& P, double a, double b, double c,
                                           double e, double f) {
+  constexpr bool FE = (SPEC == SPEC_FE);
   // Candidates, eq. 5.
   const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
   const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
   const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
-  if (P.weights == WLIN) return D0 * c0 + D1 * c1 + D2 * c2;
+  if (!FE && P.weights == WLIN) return D0 * c0 + D1 * c1 + D2 * c2;
 
   // Smoothness indicators, eq. 9-10, written through the first differences of
   // the stencil so that a sub-stencil of equal values gives IS = 0 exactly
@@ -127,7 +199,7 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
   const double IS2 = f2 * f2 + s2 * s2;
 
   double a0, a1, a2;
-  if (P.weights == WJS) {
+  if (!FE && P.weights == WJS) {
     const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
     a0 = D0 * r0 * r0;
     a1 = D1 * r1 * r1;
@@ -136,7 +208,8 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
     const double tau = __builtin_fabs(IS0 - IS2);
     double q0 = tau * rcp(IS0 + P.eps), q1 = tau * rcp(IS1 + P.eps), q2 = tau * rcp(IS2 + P.eps);
     double p0 = q0, p1 = q1, p2 = q2;
-    for (int k = 1; k < P.zpow; ++k) {
+    const int zpow = FE ? 2 : P.zpow;
+    for (int k = 1; k < zpow; ++k) {
       p0 *= q0;
       p1 *= q1;
       p2 *= q2;
@@ -148,14 +221,14 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
   const double inv = rcp(a0 + a1 + a2);
   double w0 = a0 * inv, w1 = a1 * inv, w2 = a2 * inv;
 
-  bool map = (P.weights == WFE);
-  if (P.weights == WPFE) {
+  bool map = FE || (P.weights == WFE);
+  if (!FE && P.weights == WPFE) {
     const bool inside = __builtin_fabs(w0 - D0) <= P.cv && __builtin_fabs(w1 - D1) <= P.cv &&
                         __builtin_fabs(w2 - D2) <= P.cv;
     map = !inside;
   }
   if (map) {
-    const double g0 = fe_g0(w0, P), g1 = fe_g1(w1, P), g2 = fe_g2(w2, P);
+    const double g0 = fe_g0<SPEC>(w0, P), g1 = fe_g1<SPEC>(w1, P), g2 = fe_g2<SPEC>(w2, P);
     const double ginv = rcp(g0 + g1 + g2);
     w0 = g0 * ginv;
     w1 = g1 * ginv;
@@ -258,6 +331,24 @@ __device__ __forceinline__ void project(const RoeState<ND>& r, const double* U, 
   W[ND + 1] = 0.5 * (theta - an);
 }
 
+// Field v of the projection of one node (row v of L applied to U); v is
+// uniform across a wavefront where this is used.
+template <int ND, int DIR>
+__device__ __forceinline__ double project_field(const RoeState<ND>& r, const double* U, int v) {
+  constexpr int NV = ND + 2;
+  if (v >= 2 && v < NV - 1) {
+    const int ax = tangential_axis<ND, DIR>(v - 2);
+    return U[1 + ax] - r.vel[ax] * U[0];
+  }
+  double um = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) um += r.vel[k] * U[1 + k];
+  const double theta = r.b2 * U[0] - r.b1 * um + r.b1 * U[ND + 1];
+  if (v == 1) return U[0] - theta;
+  const double an = (r.vel[DIR] * U[0] - U[1 + DIR]) * r.ic;
+  return (v == 0) ? 0.5 * (theta + an) : 0.5 * (theta - an);
+}
+
 // Right eigenvectors applied to characteristic values: U = R W.
 template <int ND, int DIR>
 __device__ __forceinline__ void unproject(const RoeState<ND>& r, const double* W, double* U) {
@@ -305,12 +396,12 @@ __device__ __forceinline__ void llf_flux(const double* UL, const double* UR, dou
 
 // Numerical flux at the midpoint between nodes s[2] and s[3] of a six-node
 // stencil s[0..5] (nodes m-2 .. m+3) along DIR.  NV = 1: scalar advection.
-template <int NV, int DIR>
+template <int NV, int DIR, int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ void midpoint_flux(const InterpParams& IP, const PhysParams& PP,
                                               const double (&s)[6][NV], double (&F)[NV]) {
   if constexpr (NV == 1) {
-    const double uL = interp5(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0]);
-    const double uR = interp5(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0]);
+    const double uL = interp5<SPEC>(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0]);
+    const double uR = interp5<SPEC>(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0]);
     F[0] = 0.5 * PP.adv * (uL + uR) - 0.5 * __builtin_fabs(PP.adv) * (uR - uL);
   } else {
     constexpr int ND = NV - 2;
@@ -322,16 +413,20 @@ __device__ __forceinline__ void midpoint_flux(const InterpParams& IP, const Phys
       for (int j = 0; j < 6; ++j) project<ND, DIR>(r, s[j], W[j]);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        WL[v] = interp5(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
-        WR[v] = interp5(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
+        WL[v] = interp5<SPEC>(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
+        WR[v] = interp5<SPEC>(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
+        // Keep the scheduler from interleaving the fields: bounded live ranges
+        // keep the kernel within 2 waves per SIMD without spills.
+        __builtin_amdgcn_sched_barrier(0);
       }
       unproject<ND, DIR>(r, WL, UL);
       unproject<ND, DIR>(r, WR, UR);
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        UL[v] = interp5(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
-        UR[v] = interp5(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
+        UL[v] = interp5<SPEC>(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
+        UR[v] = interp5<SPEC>(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     llf_flux<ND, DIR>(UL, UR, PP.gamma, F);

@@ -11,6 +11,11 @@ namespace wcns {
 
 enum SweepMode : int { MODE_RES = 0, MODE_ACC = 1, MODE_STAGE = 2 };
 
+// Which compiled specialisation of the interpolation serves these parameters.
+inline int spec_of(const InterpParams& ip) {
+  return (ip.weights == WFE && ip.zpow == 2 && ip.shared_exp) ? SPEC_FE : SPEC_GENERIC;
+}
+
 // Arguments of one directional sweep.
 struct SweepArgs {
   const double* U;      // state under the stencil, U^(k)
@@ -77,5 +82,7 @@ hipError_t launch_adjoint_dir(int nv, int dir, const AdjArgs& a, hipStream_t str
 size_t adjoint_contrib_elems(int nv, int dir, const int64_t n[3], int diff);
 
 int cfl_blocks(int64_t npts);
+// Largest x-sweep tile (midpoints) for nv conserved variables.
+int xsweep_max_tm(int nv);
 
 }  // namespace wcns

@@ -1,232 +1,209 @@
 // Forward kernels of the WCNS-FE residual on gfx950.
 //
 //  xsweep   lines along x (contiguous): one workgroup = one tile of TM
-//           midpoints; the TM+5 nodes under it are staged in LDS with the
-//           boundary ghosts applied, each lane computes one midpoint flux into
-//           LDS, then TM-3 (MND6) or TM-5 (MD6) lanes form the flux
-//           difference of one node each and write R, R+=, or the fused
-//           SSP-RK3 stage combine.  The same kernel serves regular grids and
-//           ragged batches (a tile table), looping over tiles persistently.
-//  march    lines along y or z (strided): lanes run across x so every load
-//           is a coalesced row segment; each lane marches along its line
-//           over a segment, keeping the six-node stencil and the last
-//           midpoint fluxes in registers (a sliding window), so each
-//           midpoint flux is computed once per segment.
+//           midpoints with the nodes staged in LDS; one lane per
+//           (midpoint, field, side) interpolation, then the flux and the
+//           difference (R, R+=, or the fused SSP-RK3 stage combine).  The same
+//           kernel serves regular grids and ragged batches (a longest-first
+//           tile table).
+//  (the y/z sweeps are in wcns_march.hip)
 //  cfl      two deterministic passes: per-block maxima of
 //           sum_d (|u_d| + c)/h_d (wavefront shuffles, then LDS), then one
 //           block that turns the maximum into dt = cfl / max.
 #include <hip/hip_runtime.h>
 
 #include "wcns_internal.hpp"
+#include "wcns_sweep_common.hpp"
 
 namespace wcns {
 
-__device__ __forceinline__ int64_t bc_index(int64_t j, int64_t N, int bc) {
-  if (bc == 0) {  // periodic
-    j %= N;
-    return j < 0 ? j + N : j;
-  }
-  return j < 0 ? 0 : (j >= N ? N - 1 : j);  // transmissive: zeroth-order copy
-}
-
-__device__ __forceinline__ void flag_status(int32_t* status) {
-  if (status) atomicOr(status, 1);
-}
-
-// Writes one node's result according to the sweep mode.  Un is the state
-// under the stencil at that node (needed by the stage combine).
-template <int NV, int MODE>
-__device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t vstride,
-                                     const double (&res)[NV], const double (&Un)[NV],
-                                     double dt) {
-  if constexpr (MODE == MODE_RES) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = res[v];
-  } else if constexpr (MODE == MODE_ACC) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = a.Rin[v * vstride + gidx] + res[v];
-  } else {
-    double y[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double r = res[v];
-      if (a.Rin) r += a.Rin[v * vstride + gidx];
-      double s = a.cb * __builtin_fma(dt, r, Un[v]);
-      if (a.ca != 0.0) s = __builtin_fma(a.ca, a.U0[v * vstride + gidx], s);
-      y[v] = s;
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = y[v];
-    if (!physical<NV>(y, a.pp.gamma)) flag_status(a.status);
-  }
-}
-
 // ------------------------------------------------------------------ xsweep --
-// LDS: sU[v][TM+5] then sF[v][TM] (doubles), TM = blockDim.x.
-template <int NV, int MODE, bool BATCH>
-__global__ void __launch_bounds__(256) xsweep_kernel(SweepArgs a, BatchArgs b, int64_t ntiles,
-                                                     int64_t tiles_per_line) {
+// One workgroup = one tile of TM midpoints of one line, TM lanes by 2*NV
+// slots (blockDim = (TM, 2 NV); TM is a multiple of 64, so the slot is uniform
+// across a wavefront).  Phases, separated by barriers:
+//   load   the TM + 5 nodes under the tile, ghosts applied, into LDS;
+//   roe    slot 0: Roe average of the two nodes around each midpoint;
+//   interp every lane: ONE nonlinear interpolation - field v = slot % NV of
+//          the left-biased (slot < NV) or mirrored right-biased stencil,
+//          projected on the fly from the LDS nodes;
+//   flux   slot 0: back-projection of the two states and the LLF flux;
+//   diff   slot 0, TL = TM - 3 (MND6) or TM - 5 (MD6) lanes: the flux
+//          difference of one node and the output (R, R+= or stage combine).
+// One interpolation per lane keeps the live state small (high occupancy);
+// the interpolations are ~85% of the arithmetic.
+// LDS (doubles): sU[NV][TM+5] | sR[NR][TM] | sW[2 NV][TM] | sF[NV][TM].
+template <int NV>
+struct XTile {
+  static constexpr int ND = NV > 1 ? NV - 2 : 1;
+  static constexpr int NR = NV > 1 ? NV - 2 + 6 : 0;  // vel[ND], H, c, ic, q2h, b1, b2
+  static constexpr int kMaxTM = NV <= 3 ? 128 : 64;       // midpoints per tile (upper bound)
+  static constexpr int kMaxThreads = kMaxTM * 2 * NV;
+  static size_t lds_doubles(int tm) { return (size_t)NV * (tm + 5) + (size_t)(NR + 3 * NV) * tm; }
+};
+
+template <int NV, int MODE, bool BATCH, int SPEC>
+__global__ void __launch_bounds__(XTile<NV>::kMaxThreads) xsweep_kernel(SweepArgs a, BatchArgs b, int64_t ntiles,
+                                                      int64_t tiles_per_line) {
+  constexpr int ND = XTile<NV>::ND;
+  constexpr int NR = XTile<NV>::NR;
   extern __shared__ double smem[];
   const int TM = blockDim.x;
   const int TN = TM + 5;
   double* sU = smem;
-  double* sF = smem + NV * TN;
+  double* sR = sU + NV * TN;
+  double* sW = sR + NR * TM;
+  double* sF = sW + 2 * NV * TM;
   const int t = threadIdx.x;
+  const int slot = threadIdx.y;
+  const int tid = slot * TM + t;
+  const int nthr = TM * blockDim.y;
   const int G = a.diff ? 5 : 4;
   const int TL = TM - (a.diff ? 5 : 3);
 
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    int64_t base, N, i0;
-    double ih = a.ih, dt = 0.0;
-    if constexpr (BATCH) {
-      const int p = b.tile_prob[tile];
-      base = b.offset[p];
-      N = b.offset[p + 1] - base;
-      i0 = b.tile_i0[tile];
-      ih = b.ih[p];
-      if constexpr (MODE == MODE_STAGE) {
-        dt = b.dtp[p];
-        if (dt == 0.0) continue;  // finished problem (uniform across the block)
+  const int64_t tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  int64_t base, N, i0;
+  double ih = a.ih, dt = 0.0;
+  if constexpr (BATCH) {
+    const int p = b.tile_prob[tile];
+    base = b.offset[p];
+    N = b.offset[p + 1] - base;
+    i0 = b.tile_i0[tile];
+    ih = b.ih[p];
+    if constexpr (MODE == MODE_STAGE) {
+      dt = b.dtp[p];
+      if (dt == 0.0) return;  // finished problem: uniform across the block
+    }
+  } else {
+    const int64_t line = tile / tiles_per_line;
+    i0 = (tile - line * tiles_per_line) * TL;
+    N = a.n[0];
+    base = line * N;
+    if constexpr (MODE == MODE_STAGE) dt = *a.dt;
+  }
+  const int64_t nb = i0 - G;
+  for (int idx = tid; idx < NV * TN; idx += nthr) {
+    const int v = idx / TN, k = idx - v * TN;
+    sU[v * TN + k] = a.U[v * a.npts + base + bc_index(nb + k, N, a.bc)];
+  }
+  __syncthreads();
+
+  const bool proj = (NV > 1) && a.pp.charproj;
+  if constexpr (NV > 1) {
+    if (proj && slot == 0) {
+      double UA[NV], UB[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UA[v] = sU[v * TN + t + 2];
+        UB[v] = sU[v * TN + t + 3];
+      }
+      const RoeState<ND> r = roe_average<ND>(UA, UB, a.pp.gamma);
+#pragma unroll
+      for (int k = 0; k < ND; ++k) sR[k * TM + t] = r.vel[k];
+      sR[(ND + 0) * TM + t] = r.H;
+      sR[(ND + 1) * TM + t] = r.c;
+      sR[(ND + 2) * TM + t] = r.ic;
+      sR[(ND + 3) * TM + t] = r.q2h;
+      sR[(ND + 4) * TM + t] = r.b1;
+      sR[(ND + 5) * TM + t] = r.b2;
+    }
+    __syncthreads();
+  }
+
+  {  // one interpolation per lane
+    const int side = slot >= NV;
+    const int v = side ? slot - NV : slot;
+    double w[5];
+    if (proj) {
+      if constexpr (NV > 1) {
+        RoeState<ND> r;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) r.vel[k] = sR[k * TM + t];
+        r.ic = sR[(ND + 2) * TM + t];
+        r.b1 = sR[(ND + 4) * TM + t];
+        r.b2 = sR[(ND + 5) * TM + t];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const int j = side ? 5 - q : q;
+          double U[NV];
+#pragma unroll
+          for (int c = 0; c < NV; ++c) U[c] = sU[c * TN + t + j];
+          w[q] = project_field<ND, 0>(r, U, v);
+        }
       }
     } else {
-      const int64_t line = tile / tiles_per_line;
-      i0 = (tile - line * tiles_per_line) * TL;
-      N = a.n[0];
-      base = line * N;
-      if constexpr (MODE == MODE_STAGE) dt = *a.dt;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) w[q] = sU[v * TN + t + (side ? 5 - q : q)];
     }
-    const int64_t nb = i0 - G;
-    __syncthreads();  // LDS reuse across tiles
+    sW[slot * TM + t] = interp5<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4]);
+  }
+  __syncthreads();
+
+  if (slot == 0) {  // midpoint flux
+    double F[NV];
+    if constexpr (NV == 1) {
+      const double uL = sW[t], uR = sW[TM + t];
+      F[0] = 0.5 * a.pp.adv * (uL + uR) - 0.5 * __builtin_fabs(a.pp.adv) * (uR - uL);
+    } else {
+      double WL[NV], WR[NV], UL[NV], UR[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      for (int k = t; k < TN; k += TM)
-        sU[v * TN + k] = a.U[v * a.npts + base + bc_index(nb + k, N, a.bc)];
-    __syncthreads();
-    {
-      double s[6][NV], F[NV];
+      for (int v = 0; v < NV; ++v) {
+        WL[v] = sW[v * TM + t];
+        WR[v] = sW[(NV + v) * TM + t];
+      }
+      if (proj) {
+        RoeState<ND> r;
 #pragma unroll
-      for (int j = 0; j < 6; ++j)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) s[j][v] = sU[v * TN + t + j];
-      midpoint_flux<NV, 0>(a.ip, a.pp, s, F);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sF[v * TM + t] = F[v];
-    }
-    __syncthreads();
-    const int64_t i = i0 + t;
-    if (t < TL && i < N) {
-      double res[NV], Un[NV];
-      if (a.diff == 0) {
-        double Um[NV], Up[NV], Fm[NV], Fp[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          Um[v] = sU[v * TN + t + 3];
-          Un[v] = sU[v * TN + t + 4];
-          Up[v] = sU[v * TN + t + 5];
-        }
-        node_flux<NV, 0>(a.pp, Um, Fm);
-        node_flux<NV, 0>(a.pp, Up, Fp);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const double* f = sF + v * TM + t;
-          const double d = 1.5 * (f[2] - f[1]) - 0.3 * (Fp[v] - Fm[v]) + (1.0 / 30.0) * (f[3] - f[0]);
-          res[v] = -ih * d;
-        }
+        for (int k = 0; k < ND; ++k) r.vel[k] = sR[k * TM + t];
+        r.H = sR[(ND + 0) * TM + t];
+        r.c = sR[(ND + 1) * TM + t];
+        r.q2h = sR[(ND + 3) * TM + t];
+        unproject<ND, 0>(r, WL, UL);
+        unproject<ND, 0>(r, WR, UR);
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          Un[v] = sU[v * TN + t + 5];
-          const double* f = sF + v * TM + t;
-          const double d = (75.0 / 64.0) * (f[3] - f[2]) + (-25.0 / 384.0) * (f[4] - f[1]) +
-                           (3.0 / 640.0) * (f[5] - f[0]);
-          res[v] = -ih * d;
+          UL[v] = WL[v];
+          UR[v] = WR[v];
         }
       }
-      const int64_t vstride = a.npts;
-      emit<NV, MODE>(a, base + i, vstride, res, Un, dt);
+      llf_flux<ND, 0>(UL, UR, a.pp.gamma, F);
     }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sF[v * TM + t] = F[v];
   }
-}
+  __syncthreads();
 
-// ------------------------------------------------------------------- march --
-template <int NV>
-__device__ __forceinline__ void load_node(const double* U, int64_t npts, int64_t idx,
-                                          double (&x)[NV]) {
+  const int64_t i = i0 + t;
+  if (slot == 0 && t < TL && i < N) {
+    double res[NV], Un[NV];
+    if (a.diff == 0) {
+      double Um[NV], Up[NV], Fm[NV], Fp[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) x[v] = U[v * npts + idx];
-}
-
-template <int NV, int DIR, int MODE, int DIFF>
-__global__ void __launch_bounds__(256) march_kernel(SweepArgs a, int seg, int nseg) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nx = a.n[0];
-  if (x >= nx) return;
-  const int64_t other = blockIdx.y / nseg;
-  const int64_t sidx = blockIdx.y - other * nseg;
-  int64_t N, stride, base;
-  if constexpr (DIR == 1) {
-    N = a.n[1];
-    stride = nx;
-    base = x + nx * a.n[1] * other;
-  } else {
-    N = a.n[2];
-    stride = nx * a.n[1];
-    base = x + nx * other;
-  }
-  const int64_t j0 = sidx * seg;
-  const int64_t j1 = (j0 + seg < N) ? j0 + seg : N;
-  double dt = 0.0;
-  if constexpr (MODE == MODE_STAGE) dt = *a.dt;
-
-  constexpr int NF = DIFF ? 6 : 4;   // midpoint fluxes in the window
-  constexpr int LAG = DIFF ? 2 : 1;  // output node j = m - LAG
-  double s[6][NV];
-  double Fh[NF][NV];
-  const int64_t mstart = j0 - (DIFF ? 3 : 2);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) load_node<NV>(a.U, a.npts, base + bc_index(mstart - 2 + k, N, a.bc) * stride, s[k]);
-
-  for (int64_t m = mstart; m <= j1 - 1 + (DIFF ? 2 : 1); ++m) {
-#pragma unroll
-    for (int q = 0; q < NF - 1; ++q)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Fh[q][v] = Fh[q + 1][v];
-    midpoint_flux<NV, DIR>(a.ip, a.pp, s, Fh[NF - 1]);
-    const int64_t j = m - LAG;
-    if (j >= j0) {
-      double res[NV], Un[NV];
-      if constexpr (DIFF == 0) {
-        // window: s[0] = node j-1, s[1] = node j, s[2] = node j+1;
-        // Fh[0..3] = F~ at j-3/2, j-1/2, j+1/2, j+3/2.
-        double Fm[NV], Fp[NV];
-        node_flux<NV, DIR>(a.pp, s[0], Fm);
-        node_flux<NV, DIR>(a.pp, s[2], Fp);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          Un[v] = s[1][v];
-          const double d = 1.5 * (Fh[2][v] - Fh[1][v]) - 0.3 * (Fp[v] - Fm[v]) +
-                           (1.0 / 30.0) * (Fh[3][v] - Fh[0][v]);
-          res[v] = -a.ih * d;
-        }
-      } else {
-        // s[0] = node j, Fh[0..5] = F~ at j-5/2 .. j+5/2.
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          Un[v] = s[0][v];
-          const double d = (75.0 / 64.0) * (Fh[3][v] - Fh[2][v]) +
-                           (-25.0 / 384.0) * (Fh[4][v] - Fh[1][v]) +
-                           (3.0 / 640.0) * (Fh[5][v] - Fh[0][v]);
-          res[v] = -a.ih * d;
-        }
+      for (int v = 0; v < NV; ++v) {
+        Um[v] = sU[v * TN + t + 3];
+        Un[v] = sU[v * TN + t + 4];
+        Up[v] = sU[v * TN + t + 5];
       }
-      emit<NV, MODE>(a, base + j * stride, a.npts, res, Un, dt);
+      node_flux<NV, 0>(a.pp, Um, Fm);
+      node_flux<NV, 0>(a.pp, Up, Fp);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double* f = sF + v * TM + t;
+        const double d = 1.5 * (f[2] - f[1]) - 0.3 * (Fp[v] - Fm[v]) + (1.0 / 30.0) * (f[3] - f[0]);
+        res[v] = -ih * d;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        Un[v] = sU[v * TN + t + 5];
+        const double* f = sF + v * TM + t;
+        const double d = (75.0 / 64.0) * (f[3] - f[2]) + (-25.0 / 384.0) * (f[4] - f[1]) +
+                         (3.0 / 640.0) * (f[5] - f[0]);
+        res[v] = -ih * d;
+      }
     }
-    // Slide the stencil: drop node m-2, load node m+4.
-#pragma unroll
-    for (int k = 0; k < 5; ++k)
-#pragma unroll
-      for (int v = 0; v < NV; ++v) s[k][v] = s[k + 1][v];
-    load_node<NV>(a.U, a.npts, base + bc_index(m + 4, N, a.bc) * stride, s[5]);
+    emit<NV, MODE>(a, base + i, a.npts, res, Un, dt);
   }
 }
 
@@ -349,6 +326,10 @@ __global__ void zero_kernel(double* __restrict__ y, int64_t n) {
 // --------------------------------------------------------------- launchers --
 static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+int xsweep_max_tm(int nv) {
+  return nv <= 3 ? XTile<3>::kMaxTM : XTile<5>::kMaxTM;
+}
+
 int cfl_blocks(int64_t npts) {
   int64_t b = ceil_div(npts, 256 * 8);
   if (b < 1) b = 1;
@@ -358,21 +339,27 @@ int cfl_blocks(int64_t npts) {
 
 template <int NV, int MODE, bool BATCH>
 static hipError_t xsweep_go(const SweepArgs& a, const BatchArgs& b, int tm, int64_t ntiles,
-                            int64_t tpl, int grid, hipStream_t s) {
-  const size_t lds = sizeof(double) * NV * (2 * tm + 5);
-  hipLaunchKernelGGL((xsweep_kernel<NV, MODE, BATCH>), dim3(grid), dim3(tm), lds, s, a, b,
-                     ntiles, tpl);
+                            int64_t tpl, hipStream_t s) {
+  if (tm > XTile<NV>::kMaxTM || tm % 64 != 0) return hipErrorInvalidConfiguration;
+  const size_t lds = sizeof(double) * XTile<NV>::lds_doubles(tm);
+  const dim3 block(tm, 2 * NV);
+  if (spec_of(a.ip) == SPEC_FE)
+    hipLaunchKernelGGL((xsweep_kernel<NV, MODE, BATCH, SPEC_FE>), dim3((unsigned)ntiles), block, lds,
+                       s, a, b, ntiles, tpl);
+  else
+    hipLaunchKernelGGL((xsweep_kernel<NV, MODE, BATCH, SPEC_GENERIC>), dim3((unsigned)ntiles), block,
+                       lds, s, a, b, ntiles, tpl);
   return hipGetLastError();
 }
 
 template <bool BATCH>
 static hipError_t xsweep_dispatch(int nv, int mode, const SweepArgs& a, const BatchArgs& b,
-                                  int tm, int64_t ntiles, int64_t tpl, int grid, hipStream_t s) {
+                                  int tm, int64_t ntiles, int64_t tpl, hipStream_t s) {
 #define WCNS_X(NVV)                                                                 \
   if (nv == NVV) {                                                                  \
-    if (mode == MODE_RES) return xsweep_go<NVV, MODE_RES, BATCH>(a, b, tm, ntiles, tpl, grid, s); \
-    if (mode == MODE_ACC) return xsweep_go<NVV, MODE_ACC, BATCH>(a, b, tm, ntiles, tpl, grid, s); \
-    return xsweep_go<NVV, MODE_STAGE, BATCH>(a, b, tm, ntiles, tpl, grid, s);       \
+    if (mode == MODE_RES) return xsweep_go<NVV, MODE_RES, BATCH>(a, b, tm, ntiles, tpl, s); \
+    if (mode == MODE_ACC) return xsweep_go<NVV, MODE_ACC, BATCH>(a, b, tm, ntiles, tpl, s); \
+    return xsweep_go<NVV, MODE_STAGE, BATCH>(a, b, tm, ntiles, tpl, s);       \
   }
   if constexpr (BATCH) {
     WCNS_X(3)
@@ -391,47 +378,15 @@ hipError_t launch_xsweep(int nv, const SweepArgs& a, int mode, int tm, hipStream
   const int64_t tpl = ceil_div(a.n[0], TL);
   const int64_t lines = a.n[1] * a.n[2];
   const int64_t ntiles = tpl * lines;
-  const int64_t grid = ntiles < (1 << 30) ? ntiles : (1 << 30);
+  if (ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
   BatchArgs b{};
-  return xsweep_dispatch<false>(nv, mode, a, b, tm, ntiles, tpl, (int)grid, stream);
+  return xsweep_dispatch<false>(nv, mode, a, b, tm, ntiles, tpl, stream);
 }
 
 hipError_t launch_batch_xsweep(const SweepArgs& a, const BatchArgs& b, int mode, int tm,
                                int grid, hipStream_t stream) {
-  return xsweep_dispatch<true>(3, mode, a, b, tm, b.ntiles, 1, grid, stream);
-}
-
-template <int NV, int DIR, int MODE, int DIFF>
-static hipError_t march_go(const SweepArgs& a, int seg, int bw, hipStream_t s) {
-  const int64_t N = (DIR == 1) ? a.n[1] : a.n[2];
-  const int64_t others = (DIR == 1) ? a.n[2] : a.n[1];
-  const int nseg = (int)ceil_div(N, seg);
-  if (others * nseg > 65535) return hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)ceil_div(a.n[0], bw), (unsigned)(others * nseg));
-  hipLaunchKernelGGL((march_kernel<NV, DIR, MODE, DIFF>), grid, dim3(bw), 0, s, a, seg, nseg);
-  return hipGetLastError();
-}
-
-template <int NV, int DIR>
-static hipError_t march_mode(int mode, const SweepArgs& a, int seg, int bw, hipStream_t s) {
-  if (a.diff == 0) {
-    if (mode == MODE_RES) return march_go<NV, DIR, MODE_RES, 0>(a, seg, bw, s);
-    if (mode == MODE_ACC) return march_go<NV, DIR, MODE_ACC, 0>(a, seg, bw, s);
-    return march_go<NV, DIR, MODE_STAGE, 0>(a, seg, bw, s);
-  }
-  if (mode == MODE_RES) return march_go<NV, DIR, MODE_RES, 1>(a, seg, bw, s);
-  if (mode == MODE_ACC) return march_go<NV, DIR, MODE_ACC, 1>(a, seg, bw, s);
-  return march_go<NV, DIR, MODE_STAGE, 1>(a, seg, bw, s);
-}
-
-hipError_t launch_march(int nv, int dir, const SweepArgs& a, int mode, int seg, int bw,
-                        hipStream_t stream) {
-  if (nv == 1 && dir == 1) return march_mode<1, 1>(mode, a, seg, bw, stream);
-  if (nv == 1 && dir == 2) return march_mode<1, 2>(mode, a, seg, bw, stream);
-  if (nv == 4 && dir == 1) return march_mode<4, 1>(mode, a, seg, bw, stream);
-  if (nv == 5 && dir == 1) return march_mode<5, 1>(mode, a, seg, bw, stream);
-  if (nv == 5 && dir == 2) return march_mode<5, 2>(mode, a, seg, bw, stream);
-  return hipErrorInvalidValue;
+  (void)grid;
+  return xsweep_dispatch<true>(3, mode, a, b, tm, b.ntiles, 1, stream);
 }
 
 hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double gamma,
