@@ -228,7 +228,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP64_TFLOPS,
             "traffic": None,
-            "kernel": "xsweep_kernel<3, stage, batch>",
+            "kernel": "sweep_kernel<3, x, stage, batch, FE>",
             "kernel_ms": kernel_ms,
             "flops_per_point_stage": flops_pt,
             "hbm_algorithmic_gbs": hbm_gbs,

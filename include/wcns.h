@@ -138,10 +138,12 @@ wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lam
    HIP events; synchronises the stream) and keeps the fastest in the plan and
    in a per-process cache keyed by shape.  U is not modified. */
 wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, void* stream);
-/* Current tile shapes: [0] x-sweep midpoints per tile, [1] y/z-sweep segment
-   length, [2] y/z-sweep lanes per workgroup. */
+/* Current tile shapes: [0] midpoints per tile of the x sweep (128 or 256);
+   [1], [2] midpoints along the line and adjacent x-columns per tile of the
+   y/z sweeps, one of (16,8), (16,16), (32,4), (32,8), (64,2), (64,4). */
 void wcns_plan_get_tiles(const wcns_plan* plan, int32_t tiles[3]);
-/* Sets tile shapes (validated; WCNS_EINVAL if not among the candidates). */
+/* Sets tile shapes (WCNS_EINVAL if not among the candidates or if the tile
+   would exceed 64 KB of LDS for this system). */
 wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]);
 
 /* ----- ragged batch of independent 1D problems (one persistent launch per
@@ -185,7 +187,8 @@ wcns_status wcns_batch_cfl(wcns_batch_plan* plan, const double* U, void* work, d
 wcns_status wcns_batch_stage(wcns_batch_plan* plan, int32_t stage, const double* Uk,
                              const double* U0, double* out, void* work, int32_t* status_dev,
                              void* stream);
-/* Candidate midpoints-per-tile are timed on U as in wcns_plan_autotune. */
+/* Candidate midpoints per tile (128, 256) are timed on U as in
+   wcns_plan_autotune. */
 wcns_status wcns_batch_autotune(wcns_batch_plan* plan, const double* U, void* work,
                                 void* stream);
 int32_t wcns_batch_get_tile(const wcns_batch_plan* plan);

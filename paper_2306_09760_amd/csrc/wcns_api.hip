@@ -46,9 +46,11 @@ wcns_status hip_fail(hipError_t e, const char* what) {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-const int kTmCandidates[] = {64, 128};
-const int kSegCandidates[] = {16, 32, 64};
-const int kBwCandidates[] = {64, 128, 256};
+// Tile candidates: x sweeps (and the batch) take tm midpoints per tile; y/z
+// sweeps take (tm, w) = midpoints along the line by adjacent x-columns.
+const int kTmCandidates[] = {128, 256};
+const int kYzCandidates[][2] = {{16, 8}, {16, 16}, {32, 4}, {32, 8}, {64, 2}, {64, 4}};
+const int kNumYz = 6;
 
 bool in_list(int v, const int* l, int n) {
   for (int i = 0; i < n; ++i)
@@ -212,8 +214,8 @@ wcns_status sweep_common(const wcns_plan* P, int d, SweepArgs* a) {
 }
 
 hipError_t run_sweep(const wcns_plan* P, int d, SweepArgs& a, int mode, hipStream_t s) {
-  if (d == 0) return launch_xsweep(P->nv, a, mode, P->tm, s);
-  return launch_march(P->nv, d, a, mode, P->seg, P->bw, s);
+  if (d == 0) return launch_sweep(P->nv, 0, a, mode, P->tm, 1, s);
+  return launch_sweep(P->nv, d, a, mode, P->seg, P->bw, s);
 }
 
 // R = L(U) into R.
@@ -300,9 +302,9 @@ wcns_status wcns_plan_create(const wcns_desc* desc, wcns_plan** plan) {
   P->npts = desc->n[0] * desc->n[1] * desc->n[2];
   for (int k = 0; k < 3; ++k) P->ih[k] = k < desc->ndim ? 1.0 / desc->h[k] : 0.0;
   interp_params(desc, &P->ip);
-  P->tm = 64;
+  P->tm = 128;
   P->seg = 32;
-  P->bw = 64;
+  P->bw = 4;
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     TuneKey k{desc->ndim, P->nv, desc->weights, desc->diff, desc->char_proj, desc->n[0], desc->n[1], desc->n[2]};
@@ -348,8 +350,11 @@ void wcns_plan_get_tiles(const wcns_plan* plan, int32_t tiles[3]) {
 wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]) {
   g_err.clear();
   if (!plan || !tiles) return fail(WCNS_EINVAL, "NULL argument");
-  if (!in_list(tiles[0], kTmCandidates, 2) || tiles[0] > xsweep_max_tm(plan->nv) ||
-      !in_list(tiles[1], kSegCandidates, 3) || !in_list(tiles[2], kBwCandidates, 3))
+  bool yz_ok = false;
+  for (int k = 0; k < kNumYz; ++k)
+    if (kYzCandidates[k][0] == tiles[1] && kYzCandidates[k][1] == tiles[2]) yz_ok = true;
+  if (!in_list(tiles[0], kTmCandidates, 2) || !sweep_shape_ok(plan->nv, 0, tiles[0], 1) ||
+      !yz_ok || !sweep_shape_ok(plan->nv, 1, tiles[1], tiles[2]))
     return fail(WCNS_EINVAL, "tile shape (%d, %d, %d) not among the candidates", tiles[0], tiles[1],
                 tiles[2]);
   plan->tm = tiles[0];
@@ -502,7 +507,7 @@ wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, voi
   float best = 1e30f;
   int best_tm = plan->tm;
   for (int tm : kTmCandidates) {
-    if (tm > xsweep_max_tm(plan->nv)) continue;
+    if (!sweep_shape_ok(plan->nv, 0, tm, 1)) continue;
     plan->tm = tm;
     float ms;
     if ((st = time_sweep(0, &ms)) != WCNS_OK) break;
@@ -515,8 +520,10 @@ wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, voi
   if (st == WCNS_OK && plan->d.ndim > 1) {
     best = 1e30f;
     int bs = plan->seg, bb = plan->bw;
-    for (int seg : kSegCandidates)
-      for (int bw : kBwCandidates) {
+    for (int k = 0; k < kNumYz; ++k) {
+      {
+        const int seg = kYzCandidates[k][0], bw = kYzCandidates[k][1];
+        if (!sweep_shape_ok(plan->nv, 1, seg, bw)) continue;
         plan->seg = seg;
         plan->bw = bw;
         float ms;
@@ -527,6 +534,7 @@ wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, voi
           bb = bw;
         }
       }
+    }
     plan->seg = bs;
     plan->bw = bb;
   }
@@ -568,7 +576,7 @@ static wcns_status batch_build_tiles(wcns_batch_plan* B) {
   WCNS_HIP(hipMemcpy(B->d_tile_prob, tp.data(), sizeof(int32_t) * tp.size(), hipMemcpyHostToDevice), "copy tiles");
   WCNS_HIP(hipMemcpy(B->d_tile_i0, ti.data(), sizeof(int32_t) * ti.size(), hipMemcpyHostToDevice), "copy tiles");
   // Persistent grid: enough resident workgroups to fill every CU a few times.
-  B->grid = std::min<int64_t>(B->ntiles, (int64_t)B->cus * 8);
+  B->grid = B->ntiles;
   if (B->exec) {
     hipGraphExecDestroy(B->exec);
     B->exec = nullptr;
@@ -672,7 +680,7 @@ wcns_status wcns_batch_residual(wcns_batch_plan* B, const double* U, double* R, 
   batch_args(B, nullptr, &a, &b);
   a.U = U;
   a.out = R;
-  WCNS_HIP(launch_batch_xsweep(a, b, MODE_RES, B->tm, B->grid, (hipStream_t)stream), "batch residual launch");
+  WCNS_HIP(launch_batch_sweep(a, b, MODE_RES, B->tm, (hipStream_t)stream), "batch residual launch");
   return WCNS_OK;
 }
 
@@ -697,7 +705,7 @@ static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work,
     a.out = dst[k];
     a.ca = ca[k];
     a.cb = cb[k];
-    WCNS_HIP(launch_batch_xsweep(a, b, MODE_STAGE, B->tm, B->grid, s), "batch stage launch");
+    WCNS_HIP(launch_batch_sweep(a, b, MODE_STAGE, B->tm, s), "batch stage launch");
   }
   return WCNS_OK;
 }
@@ -770,7 +778,7 @@ wcns_status wcns_batch_stage(wcns_batch_plan* B, int32_t stage, const double* Uk
   a.out = out;
   a.ca = ca[stage - 1];
   a.cb = cb[stage - 1];
-  WCNS_HIP(launch_batch_xsweep(a, b, MODE_STAGE, B->tm, B->grid, (hipStream_t)stream),
+  WCNS_HIP(launch_batch_sweep(a, b, MODE_STAGE, B->tm, (hipStream_t)stream),
            "batch stage launch");
   return WCNS_OK;
 }
@@ -787,7 +795,7 @@ int32_t wcns_batch_get_tile(const wcns_batch_plan* B) { return B ? B->tm : 0; }
 wcns_status wcns_batch_set_tile(wcns_batch_plan* B, int32_t tile) {
   g_err.clear();
   if (!B) return fail(WCNS_EINVAL, "NULL plan");
-  if (!in_list(tile, kTmCandidates, 2) || tile > xsweep_max_tm(3))
+  if (!in_list(tile, kTmCandidates, 2) || !sweep_shape_ok(3, 0, tile, 1))
     return fail(WCNS_EINVAL, "tile %d not among the candidates", tile);
   if (tile == B->tm) return WCNS_OK;
   B->tm = tile;
@@ -815,7 +823,7 @@ wcns_status wcns_batch_autotune(wcns_batch_plan* B, const double* U, void* work,
     a.out = out;
     for (int r = 0; r < 4 && st == WCNS_OK; ++r) {
       if (r == 1 && hipEventRecord(e0, s) != hipSuccess) st = fail(WCNS_EDEVICE, "event record");
-      hipError_t e = launch_batch_xsweep(a, b, MODE_RES, B->tm, B->grid, s);
+      hipError_t e = launch_batch_sweep(a, b, MODE_RES, B->tm, s);
       if (e != hipSuccess) st = hip_fail(e, "autotune launch");
     }
     if (st != WCNS_OK) break;

@@ -45,13 +45,23 @@ struct BatchArgs {
   int32_t nprob;
 };
 
-// Launchers (wcns_kernels.hip).  All enqueue on `stream` and return the
-// hipError_t of the launch.
-hipError_t launch_xsweep(int nv, const SweepArgs& a, int mode, int tm, hipStream_t stream);
-hipError_t launch_march(int nv, int dir, const SweepArgs& a, int mode, int seg, int bw,
+// Geometry of a sweep's tiles: tm midpoints along the sweep direction by w
+// adjacent x-columns (w = 1 along x); tm*w is 128 or 256 (powers of two).
+struct TileGeom {
+  int tm, w, lw, ltmw;   // lw = log2 w, ltmw = log2 (tm w)
+  int tl;                // nodes per tile and column: tm - 3 (MND6) or tm - 5 (MD6)
+  int64_t segs;          // tiles along one line
+  int64_t xgroups;       // column groups across x (1 along x)
+  int64_t ntiles;
+};
+
+// Launchers.  All enqueue on `stream` and return the hipError_t of the launch
+// (hipErrorInvalidConfiguration for a tile shape that sweep_shape_ok rejects).
+bool sweep_shape_ok(int nv, int dir, int tm, int w);
+hipError_t launch_sweep(int nv, int dir, const SweepArgs& a, int mode, int tm, int w,
                         hipStream_t stream);
-hipError_t launch_batch_xsweep(const SweepArgs& a, const BatchArgs& b, int mode, int tm,
-                               int grid, hipStream_t stream);
+hipError_t launch_batch_sweep(const SweepArgs& a, const BatchArgs& b, int mode, int tm,
+                              hipStream_t stream);
 hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double gamma,
                       const double* ih, const double* adv, double cfl, double* partial,
                       int nblocks, double* dt_out, hipStream_t stream);
@@ -82,7 +92,5 @@ hipError_t launch_adjoint_dir(int nv, int dir, const AdjArgs& a, hipStream_t str
 size_t adjoint_contrib_elems(int nv, int dir, const int64_t n[3], int diff);
 
 int cfl_blocks(int64_t npts);
-// Largest x-sweep tile (midpoints) for nv conserved variables.
-int xsweep_max_tm(int nv);
 
 }  // namespace wcns

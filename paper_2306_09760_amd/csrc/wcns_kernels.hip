@@ -1,211 +1,14 @@
-// Forward kernels of the WCNS-FE residual on gfx950.
+// Time-step and elementwise kernels of the WCNS-FE library on gfx950 (the
+// directional sweeps are in wcns_sweep.hip).
 //
-//  xsweep   lines along x (contiguous): one workgroup = one tile of TM
-//           midpoints with the nodes staged in LDS; one lane per
-//           (midpoint, field, side) interpolation, then the flux and the
-//           difference (R, R+=, or the fused SSP-RK3 stage combine).  The same
-//           kernel serves regular grids and ragged batches (a longest-first
-//           tile table).
-//  (the y/z sweeps are in wcns_march.hip)
 //  cfl      two deterministic passes: per-block maxima of
 //           sum_d (|u_d| + c)/h_d (wavefront shuffles, then LDS), then one
 //           block that turns the maximum into dt = cfl / max.
 #include <hip/hip_runtime.h>
 
 #include "wcns_internal.hpp"
-#include "wcns_sweep_common.hpp"
 
 namespace wcns {
-
-// ------------------------------------------------------------------ xsweep --
-// One workgroup = one tile of TM midpoints of one line, TM lanes by 2*NV
-// slots (blockDim = (TM, 2 NV); TM is a multiple of 64, so the slot is uniform
-// across a wavefront).  Phases, separated by barriers:
-//   load   the TM + 5 nodes under the tile, ghosts applied, into LDS;
-//   roe    slot 0: Roe average of the two nodes around each midpoint;
-//   interp every lane: ONE nonlinear interpolation - field v = slot % NV of
-//          the left-biased (slot < NV) or mirrored right-biased stencil,
-//          projected on the fly from the LDS nodes;
-//   flux   slot 0: back-projection of the two states and the LLF flux;
-//   diff   slot 0, TL = TM - 3 (MND6) or TM - 5 (MD6) lanes: the flux
-//          difference of one node and the output (R, R+= or stage combine).
-// One interpolation per lane keeps the live state small (high occupancy);
-// the interpolations are ~85% of the arithmetic.
-// LDS (doubles): sU[NV][TM+5] | sR[NR][TM] | sW[2 NV][TM] | sF[NV][TM].
-template <int NV>
-struct XTile {
-  static constexpr int ND = NV > 1 ? NV - 2 : 1;
-  static constexpr int NR = NV > 1 ? NV - 2 + 6 : 0;  // vel[ND], H, c, ic, q2h, b1, b2
-  static constexpr int kMaxTM = NV <= 3 ? 128 : 64;       // midpoints per tile (upper bound)
-  static constexpr int kMaxThreads = kMaxTM * 2 * NV;
-  static size_t lds_doubles(int tm) { return (size_t)NV * (tm + 5) + (size_t)(NR + 3 * NV) * tm; }
-};
-
-template <int NV, int MODE, bool BATCH, int SPEC>
-__global__ void __launch_bounds__(XTile<NV>::kMaxThreads) xsweep_kernel(SweepArgs a, BatchArgs b, int64_t ntiles,
-                                                      int64_t tiles_per_line) {
-  constexpr int ND = XTile<NV>::ND;
-  constexpr int NR = XTile<NV>::NR;
-  extern __shared__ double smem[];
-  const int TM = blockDim.x;
-  const int TN = TM + 5;
-  double* sU = smem;
-  double* sR = sU + NV * TN;
-  double* sW = sR + NR * TM;
-  double* sF = sW + 2 * NV * TM;
-  const int t = threadIdx.x;
-  const int slot = threadIdx.y;
-  const int tid = slot * TM + t;
-  const int nthr = TM * blockDim.y;
-  const int G = a.diff ? 5 : 4;
-  const int TL = TM - (a.diff ? 5 : 3);
-
-  const int64_t tile = blockIdx.x;
-  if (tile >= ntiles) return;
-  int64_t base, N, i0;
-  double ih = a.ih, dt = 0.0;
-  if constexpr (BATCH) {
-    const int p = b.tile_prob[tile];
-    base = b.offset[p];
-    N = b.offset[p + 1] - base;
-    i0 = b.tile_i0[tile];
-    ih = b.ih[p];
-    if constexpr (MODE == MODE_STAGE) {
-      dt = b.dtp[p];
-      if (dt == 0.0) return;  // finished problem: uniform across the block
-    }
-  } else {
-    const int64_t line = tile / tiles_per_line;
-    i0 = (tile - line * tiles_per_line) * TL;
-    N = a.n[0];
-    base = line * N;
-    if constexpr (MODE == MODE_STAGE) dt = *a.dt;
-  }
-  const int64_t nb = i0 - G;
-  for (int idx = tid; idx < NV * TN; idx += nthr) {
-    const int v = idx / TN, k = idx - v * TN;
-    sU[v * TN + k] = a.U[v * a.npts + base + bc_index(nb + k, N, a.bc)];
-  }
-  __syncthreads();
-
-  const bool proj = (NV > 1) && a.pp.charproj;
-  if constexpr (NV > 1) {
-    if (proj && slot == 0) {
-      double UA[NV], UB[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        UA[v] = sU[v * TN + t + 2];
-        UB[v] = sU[v * TN + t + 3];
-      }
-      const RoeState<ND> r = roe_average<ND>(UA, UB, a.pp.gamma);
-#pragma unroll
-      for (int k = 0; k < ND; ++k) sR[k * TM + t] = r.vel[k];
-      sR[(ND + 0) * TM + t] = r.H;
-      sR[(ND + 1) * TM + t] = r.c;
-      sR[(ND + 2) * TM + t] = r.ic;
-      sR[(ND + 3) * TM + t] = r.q2h;
-      sR[(ND + 4) * TM + t] = r.b1;
-      sR[(ND + 5) * TM + t] = r.b2;
-    }
-    __syncthreads();
-  }
-
-  {  // one interpolation per lane
-    const int side = slot >= NV;
-    const int v = side ? slot - NV : slot;
-    double w[5];
-    if (proj) {
-      if constexpr (NV > 1) {
-        RoeState<ND> r;
-#pragma unroll
-        for (int k = 0; k < ND; ++k) r.vel[k] = sR[k * TM + t];
-        r.ic = sR[(ND + 2) * TM + t];
-        r.b1 = sR[(ND + 4) * TM + t];
-        r.b2 = sR[(ND + 5) * TM + t];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          const int j = side ? 5 - q : q;
-          double U[NV];
-#pragma unroll
-          for (int c = 0; c < NV; ++c) U[c] = sU[c * TN + t + j];
-          w[q] = project_field<ND, 0>(r, U, v);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 5; ++q) w[q] = sU[v * TN + t + (side ? 5 - q : q)];
-    }
-    sW[slot * TM + t] = interp5<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4]);
-  }
-  __syncthreads();
-
-  if (slot == 0) {  // midpoint flux
-    double F[NV];
-    if constexpr (NV == 1) {
-      const double uL = sW[t], uR = sW[TM + t];
-      F[0] = 0.5 * a.pp.adv * (uL + uR) - 0.5 * __builtin_fabs(a.pp.adv) * (uR - uL);
-    } else {
-      double WL[NV], WR[NV], UL[NV], UR[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        WL[v] = sW[v * TM + t];
-        WR[v] = sW[(NV + v) * TM + t];
-      }
-      if (proj) {
-        RoeState<ND> r;
-#pragma unroll
-        for (int k = 0; k < ND; ++k) r.vel[k] = sR[k * TM + t];
-        r.H = sR[(ND + 0) * TM + t];
-        r.c = sR[(ND + 1) * TM + t];
-        r.q2h = sR[(ND + 3) * TM + t];
-        unproject<ND, 0>(r, WL, UL);
-        unproject<ND, 0>(r, WR, UR);
-      } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          UL[v] = WL[v];
-          UR[v] = WR[v];
-        }
-      }
-      llf_flux<ND, 0>(UL, UR, a.pp.gamma, F);
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) sF[v * TM + t] = F[v];
-  }
-  __syncthreads();
-
-  const int64_t i = i0 + t;
-  if (slot == 0 && t < TL && i < N) {
-    double res[NV], Un[NV];
-    if (a.diff == 0) {
-      double Um[NV], Up[NV], Fm[NV], Fp[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        Um[v] = sU[v * TN + t + 3];
-        Un[v] = sU[v * TN + t + 4];
-        Up[v] = sU[v * TN + t + 5];
-      }
-      node_flux<NV, 0>(a.pp, Um, Fm);
-      node_flux<NV, 0>(a.pp, Up, Fp);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const double* f = sF + v * TM + t;
-        const double d = 1.5 * (f[2] - f[1]) - 0.3 * (Fp[v] - Fm[v]) + (1.0 / 30.0) * (f[3] - f[0]);
-        res[v] = -ih * d;
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        Un[v] = sU[v * TN + t + 5];
-        const double* f = sF + v * TM + t;
-        const double d = (75.0 / 64.0) * (f[3] - f[2]) + (-25.0 / 384.0) * (f[4] - f[1]) +
-                         (3.0 / 640.0) * (f[5] - f[0]);
-        res[v] = -ih * d;
-      }
-    }
-    emit<NV, MODE>(a, base + i, a.npts, res, Un, dt);
-  }
-}
 
 // --------------------------------------------------------------------- CFL --
 __device__ __forceinline__ double wave_max(double v) {
@@ -326,67 +129,11 @@ __global__ void zero_kernel(double* __restrict__ y, int64_t n) {
 // --------------------------------------------------------------- launchers --
 static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-int xsweep_max_tm(int nv) {
-  return nv <= 3 ? XTile<3>::kMaxTM : XTile<5>::kMaxTM;
-}
-
 int cfl_blocks(int64_t npts) {
   int64_t b = ceil_div(npts, 256 * 8);
   if (b < 1) b = 1;
   if (b > 2048) b = 2048;
   return (int)b;
-}
-
-template <int NV, int MODE, bool BATCH>
-static hipError_t xsweep_go(const SweepArgs& a, const BatchArgs& b, int tm, int64_t ntiles,
-                            int64_t tpl, hipStream_t s) {
-  if (tm > XTile<NV>::kMaxTM || tm % 64 != 0) return hipErrorInvalidConfiguration;
-  const size_t lds = sizeof(double) * XTile<NV>::lds_doubles(tm);
-  const dim3 block(tm, 2 * NV);
-  if (spec_of(a.ip) == SPEC_FE)
-    hipLaunchKernelGGL((xsweep_kernel<NV, MODE, BATCH, SPEC_FE>), dim3((unsigned)ntiles), block, lds,
-                       s, a, b, ntiles, tpl);
-  else
-    hipLaunchKernelGGL((xsweep_kernel<NV, MODE, BATCH, SPEC_GENERIC>), dim3((unsigned)ntiles), block,
-                       lds, s, a, b, ntiles, tpl);
-  return hipGetLastError();
-}
-
-template <bool BATCH>
-static hipError_t xsweep_dispatch(int nv, int mode, const SweepArgs& a, const BatchArgs& b,
-                                  int tm, int64_t ntiles, int64_t tpl, hipStream_t s) {
-#define WCNS_X(NVV)                                                                 \
-  if (nv == NVV) {                                                                  \
-    if (mode == MODE_RES) return xsweep_go<NVV, MODE_RES, BATCH>(a, b, tm, ntiles, tpl, s); \
-    if (mode == MODE_ACC) return xsweep_go<NVV, MODE_ACC, BATCH>(a, b, tm, ntiles, tpl, s); \
-    return xsweep_go<NVV, MODE_STAGE, BATCH>(a, b, tm, ntiles, tpl, s);       \
-  }
-  if constexpr (BATCH) {
-    WCNS_X(3)
-  } else {
-    WCNS_X(1)
-    WCNS_X(3)
-    WCNS_X(4)
-    WCNS_X(5)
-  }
-#undef WCNS_X
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_xsweep(int nv, const SweepArgs& a, int mode, int tm, hipStream_t stream) {
-  const int TL = tm - (a.diff ? 5 : 3);
-  const int64_t tpl = ceil_div(a.n[0], TL);
-  const int64_t lines = a.n[1] * a.n[2];
-  const int64_t ntiles = tpl * lines;
-  if (ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-  BatchArgs b{};
-  return xsweep_dispatch<false>(nv, mode, a, b, tm, ntiles, tpl, stream);
-}
-
-hipError_t launch_batch_xsweep(const SweepArgs& a, const BatchArgs& b, int mode, int tm,
-                               int grid, hipStream_t stream) {
-  (void)grid;
-  return xsweep_dispatch<true>(3, mode, a, b, tm, b.ntiles, 1, stream);
 }
 
 hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double gamma,

@@ -31,7 +31,7 @@ def _cols(U, meta, p):
 
 
 @pytest.mark.parametrize("weights,xi", [("fe", 100.0), ("fe", 1e6), ("z", 100.0), ("js", 100.0)])
-@pytest.mark.parametrize("tile", [64, 128])
+@pytest.mark.parametrize("tile", [128, 256])
 def test_batch_residual(lib, ora, W, weights, xi, tile):
     prob, U, meta = _small_batch(W)
     say("batch residual", weights, xi, tile)
