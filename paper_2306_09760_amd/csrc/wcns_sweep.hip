@@ -3,9 +3,10 @@
 //
 // A workgroup of 256 lanes owns one tile: TM midpoints along the sweep
 // direction by W adjacent x-columns (W = 1 for the x direction; for y and z
-// the columns make the global loads coalesced rows).  TM*W is 128 or 256.
-// Phases, separated by barriers, with every lane looping over the phase's
-// tasks (no wavefront idles while one phase belongs to a subset of lanes):
+// the columns make the global loads coalesced rows).  TM*W is 128 or 256 and
+// both are compile-time, so every LDS address is a lane base plus an
+// immediate offset.  Phases, separated by barriers, with every lane looping
+// over the phase's tasks (no wavefront idles through a short phase):
 //   load    the TM+5 nodes of every column into LDS, ghosts applied;
 //   roe     Roe average of the two nodes around each midpoint;
 //   interp  one task = ONE nonlinear interpolation: field v of the
@@ -16,8 +17,8 @@
 //           Lax-Friedrichs flux;
 //   diff    MND6 or MD6 flux difference of TL = TM-3 (TM-5) nodes per
 //           column, written as R, R+= or the fused SSP-RK3 stage combine.
-// One interpolation per task keeps the live state small (about 50 VGPRs),
-// so occupancy, not the register file, bounds the kernel.
+// One interpolation per task keeps the live state small (under 100 VGPRs),
+// so the kernel runs several workgroups per CU.
 // LDS (doubles): sU[NV][TM+5][W] | sR[NR][TM*W] | sW[2 NV][TM*W]; the flux
 // overwrites sW rows 0..NV-1 (each task reads its midpoint's two states
 // before writing that midpoint's flux).
@@ -28,28 +29,34 @@
 
 namespace wcns {
 
-template <int NV>
+template <int NV, int TM, int W>
 struct SweepLayout {
   static constexpr int ND = NV > 1 ? NV - 2 : 1;
   static constexpr int NR = NV > 1 ? NV - 2 + 6 : 0;  // vel[ND], H, c, ic, q2h, b1, b2
-  static size_t lds_doubles(int tm, int w) {
-    return (size_t)NV * (tm + 5) * w + (size_t)(NR + 2 * NV) * tm * w;
-  }
+  static constexpr int TN = TM + 5;                    // nodes per column
+  static constexpr int TMW = TM * W;                   // midpoints per tile
+  static constexpr int SV = TN * W;                    // LDS stride between variables
+  static constexpr int LW = W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4;
+  static constexpr int LTMW = TMW == 128 ? 7 : 8;
+  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(NR + 2 * NV) * TMW;
+  static_assert(TMW == 128 || TMW == 256, "tile must hold 128 or 256 midpoints");
+  static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
 
-template <int NV, int DIR, int MODE, bool BATCH, int SPEC>
-__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g) {
-  constexpr int ND = SweepLayout<NV>::ND;
-  constexpr int NR = SweepLayout<NV>::NR;
+template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
+__global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g,
+                                                    int mode) {
+  using L = SweepLayout<NV, TM, W>;
+  constexpr int ND = L::ND, NR = L::NR, TN = L::TN, TMW = L::TMW, SV = L::SV;
+  constexpr int LW = L::LW, LTMW = L::LTMW;
+  constexpr int NT = 256;
   extern __shared__ double smem[];
-  const int TM = g.tm, W = g.w, LW = g.lw, LTMW = g.ltmw;
-  const int TN = TM + 5, TMW = TM * W;
   double* sU = smem;
-  double* sR = sU + NV * TN * W;
+  double* sR = sU + NV * SV;
   double* sW = sR + NR * TMW;
   const int tid = threadIdx.x;
-  constexpr int NT = 256;
   const int G = a.diff ? 5 : 4;
+  const int TL = TM - (a.diff ? 5 : 3);
 
   const int64_t tile = blockIdx.x;
   if (tile >= g.ntiles) return;
@@ -63,14 +70,14 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
     stride = 1;
     i0 = b.tile_i0[tile];
     ih = b.ih[p];
-    if constexpr (MODE == MODE_STAGE) {
+    if (mode == MODE_STAGE) {
       dt = b.dtp[p];
       if (dt == 0.0) return;  // finished problem: uniform across the block
     }
   } else {
     const int64_t seg = tile % g.segs;
     const int64_t r = tile / g.segs;
-    i0 = seg * g.tl;
+    i0 = seg * TL;
     if constexpr (DIR == 0) {
       N = a.n[0];
       base = r * N;
@@ -90,18 +97,18 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
         base = x0 + other * a.n[0];
       }
     }
-    if constexpr (MODE == MODE_STAGE) dt = *a.dt;
+    if (mode == MODE_STAGE) dt = *a.dt;
   }
   const int64_t nb = i0 - G;
 
   // load
+  for (int idx = tid; idx < SV; idx += NT) {
+    const int k = idx >> LW, c = idx & (W - 1);
+    const int cc = c < ncol ? c : ncol - 1;
+    const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
-    for (int idx = tid; idx < TN * W; idx += NT) {
-      const int k = idx >> LW, c = idx & (W - 1);
-      const int cc = c < ncol ? c : ncol - 1;
-      sU[(v * TN + k) * W + c] = a.U[v * a.npts + base + bc_index(nb + k, N, a.bc) * stride + cc];
-    }
+    for (int v = 0; v < NV; ++v) sU[v * SV + idx] = a.U[v * a.npts + gi];
+  }
   __syncthreads();
 
   const bool proj = (NV > 1) && a.pp.charproj;
@@ -109,22 +116,24 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
     if (proj) {
 #pragma unroll 1
       for (int q = tid; q < TMW; q += NT) {
-        const int m = q >> LW, c = q & (W - 1);
+        // node m+2 of column c sits at LDS index q + 2W (q = m W + c)
+        const double* u = sU + q + 2 * W;
         double UA[NV], UB[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          UA[v] = sU[(v * TN + m + 2) * W + c];
-          UB[v] = sU[(v * TN + m + 3) * W + c];
+          UA[v] = u[v * SV];
+          UB[v] = u[v * SV + W];
         }
         const RoeState<ND> rs = roe_average<ND>(UA, UB, a.pp.gamma);
+        double* r = sR + q;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) sR[k * TMW + q] = rs.vel[k];
-        sR[(ND + 0) * TMW + q] = rs.H;
-        sR[(ND + 1) * TMW + q] = rs.c;
-        sR[(ND + 2) * TMW + q] = rs.ic;
-        sR[(ND + 3) * TMW + q] = rs.q2h;
-        sR[(ND + 4) * TMW + q] = rs.b1;
-        sR[(ND + 5) * TMW + q] = rs.b2;
+        for (int k = 0; k < ND; ++k) r[k * TMW] = rs.vel[k];
+        r[(ND + 0) * TMW] = rs.H;
+        r[(ND + 1) * TMW] = rs.c;
+        r[(ND + 2) * TMW] = rs.ic;
+        r[(ND + 3) * TMW] = rs.q2h;
+        r[(ND + 4) * TMW] = rs.b1;
+        r[(ND + 5) * TMW] = rs.b2;
       }
       __syncthreads();
     }
@@ -134,33 +143,49 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
 #pragma unroll 1
   for (int q = tid; q < 2 * NV * TMW; q += NT) {
     const int slot = q >> LTMW;
-    const int rem = q & (TMW - 1);
-    const int m = rem >> LW, c = rem & (W - 1);
+    const int rem = q & (TMW - 1);  // = m W + c
     const int side = slot >= NV;
     const int v = side ? slot - NV : slot;
+    const double* u = sU + rem;     // node m of column c; node m + j at u[j W]
     double w[5];
     if (proj) {
       if constexpr (NV > 1) {
         RoeState<ND> rs;
+        const double* r = sR + rem;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) rs.vel[k] = sR[k * TMW + rem];
-        rs.ic = sR[(ND + 2) * TMW + rem];
-        rs.b1 = sR[(ND + 4) * TMW + rem];
-        rs.b2 = sR[(ND + 5) * TMW + rem];
+        for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
+        rs.ic = r[(ND + 2) * TMW];
+        rs.b1 = r[(ND + 4) * TMW];
+        rs.b2 = r[(ND + 5) * TMW];
+        if (side == 0) {
 #pragma unroll
-        for (int s = 0; s < 5; ++s) {
-          const int k = m + (side ? 5 - s : s);
-          double U[NV];
+          for (int s = 0; s < 5; ++s) {
+            double U[NV];
 #pragma unroll
-          for (int e = 0; e < NV; ++e) U[e] = sU[(e * TN + k) * W + c];
-          w[s] = project_field<ND, DIR>(rs, U, v);
+            for (int e = 0; e < NV; ++e) U[e] = u[e * SV + s * W];
+            w[s] = project_field<ND, DIR>(rs, U, v);
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < 5; ++s) {
+            double U[NV];
+#pragma unroll
+            for (int e = 0; e < NV; ++e) U[e] = u[e * SV + (5 - s) * W];
+            w[s] = project_field<ND, DIR>(rs, U, v);
+          }
         }
       }
     } else {
+      const double* uv = u + v * SV;
+      if (side == 0) {
 #pragma unroll
-      for (int s = 0; s < 5; ++s) w[s] = sU[(v * TN + m + (side ? 5 - s : s)) * W + c];
+        for (int s = 0; s < 5; ++s) w[s] = uv[s * W];
+      } else {
+#pragma unroll
+        for (int s = 0; s < 5; ++s) w[s] = uv[(5 - s) * W];
+      }
     }
-    sW[slot * TMW + rem] = interp5<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4]);
+    sW[q] = interp5<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4]);  // q = slot TMW + rem
   }
   __syncthreads();
 
@@ -180,11 +205,12 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
       }
       if (proj) {
         RoeState<ND> rs;
+        const double* r = sR + q;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) rs.vel[k] = sR[k * TMW + q];
-        rs.H = sR[(ND + 0) * TMW + q];
-        rs.c = sR[(ND + 1) * TMW + q];
-        rs.q2h = sR[(ND + 3) * TMW + q];
+        for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
+        rs.H = r[(ND + 0) * TMW];
+        rs.c = r[(ND + 1) * TMW];
+        rs.q2h = r[(ND + 3) * TMW];
         unproject<ND, DIR>(rs, WL, UL);
         unproject<ND, DIR>(rs, WR, UR);
       } else {
@@ -202,88 +228,92 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
   __syncthreads();
 
   // flux difference and output
-  const double* sF = sW;
 #pragma unroll 1
-  for (int q = tid; q < g.tl * W; q += NT) {
+  for (int q = tid; q < TL * W; q += NT) {
     const int t = q >> LW, c = q & (W - 1);
     const int64_t i = i0 + t;
     if (i >= N || c >= ncol) continue;
+    const double* f = sW + q;        // F~ of midpoint t + k of column c at f[k W]
+    const double* u = sU + q;        // node t + k of column c at u[k W]
     double res[NV], Un[NV];
     if (a.diff == 0) {
       double Um[NV], Up[NV], Fm[NV], Fp[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Um[v] = sU[(v * TN + t + 3) * W + c];
-        Un[v] = sU[(v * TN + t + 4) * W + c];
-        Up[v] = sU[(v * TN + t + 5) * W + c];
+        Um[v] = u[v * SV + 3 * W];
+        Un[v] = u[v * SV + 4 * W];
+        Up[v] = u[v * SV + 5 * W];
       }
       node_flux<NV, DIR>(a.pp, Um, Fm);
       node_flux<NV, DIR>(a.pp, Up, Fp);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double* f = sF + v * TMW + t * W + c;  // f[k W] = F~ at midpoint t + k
-        const double d = 1.5 * (f[2 * W] - f[W]) - 0.3 * (Fp[v] - Fm[v]) +
-                         (1.0 / 30.0) * (f[3 * W] - f[0]);
+        const double* fv = f + v * TMW;
+        const double d = 1.5 * (fv[2 * W] - fv[W]) - 0.3 * (Fp[v] - Fm[v]) +
+                         (1.0 / 30.0) * (fv[3 * W] - fv[0]);
         res[v] = -ih * d;
       }
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Un[v] = sU[(v * TN + t + 5) * W + c];
-        const double* f = sF + v * TMW + t * W + c;
-        const double d = (75.0 / 64.0) * (f[3 * W] - f[2 * W]) +
-                         (-25.0 / 384.0) * (f[4 * W] - f[W]) + (3.0 / 640.0) * (f[5 * W] - f[0]);
+        Un[v] = u[v * SV + 5 * W];
+        const double* fv = f + v * TMW;
+        const double d = (75.0 / 64.0) * (fv[3 * W] - fv[2 * W]) +
+                         (-25.0 / 384.0) * (fv[4 * W] - fv[W]) + (3.0 / 640.0) * (fv[5 * W] - fv[0]);
         res[v] = -ih * d;
       }
     }
-    emit<NV, MODE>(a, base + i * stride + c, a.npts, res, Un, dt);
+    emit_rt<NV>(mode, a, base + i * stride + c, a.npts, res, Un, dt);
   }
 }
 
 // --------------------------------------------------------------- launchers --
 static inline int64_t ceil_div64(int64_t x, int64_t y) { return (x + y - 1) / y; }
-static inline int ilog2(int x) {
-  int l = 0;
-  while ((1 << l) < x) ++l;
-  return l;
-}
 
+// Compiled tile shapes: x direction and batch tm in {128, 256}; y/z (tm, w)
+// in {(16, 8), (32, 4), (32, 8), (64, 4)}.
 bool sweep_shape_ok(int nv, int dir, int tm, int w) {
-  if (tm < 16 || w < 1 || (tm & (tm - 1)) || (w & (w - 1))) return false;
-  if (dir == 0 && w != 1) return false;
-  const int tmw = tm * w;
-  if (tmw != 128 && tmw != 256) return false;
-  const size_t lds = sizeof(double) * ((size_t)nv * (tm + 5) * w + (size_t)(nv + 4 + 2 * nv) * tmw);
+  if (dir == 0) return w == 1 && (tm == 128 || tm == 256);
+  const bool known = (tm == 16 && w == 8) || (tm == 32 && w == 4) || (tm == 32 && w == 8) ||
+                     (tm == 64 && w == 4);
+  if (!known) return false;
+  const size_t lds = sizeof(double) * ((size_t)nv * (tm + 5) * w + (size_t)(3 * nv + 4) * tm * w);
   return lds <= 64 * 1024;
 }
 
-template <int NV, int DIR, int MODE, bool BATCH>
-static hipError_t sweep_go(const SweepArgs& a, const BatchArgs& b, const TileGeom& g,
+template <int NV, int DIR, bool BATCH, int TM, int W>
+static hipError_t sweep_go(const SweepArgs& a, const BatchArgs& b, const TileGeom& g, int mode,
                            hipStream_t s) {
-  const size_t lds = sizeof(double) * SweepLayout<NV>::lds_doubles(g.tm, g.w);
+  const size_t lds = sizeof(double) * SweepLayout<NV, TM, W>::lds_doubles;
   if (spec_of(a.ip) == SPEC_FE)
-    hipLaunchKernelGGL((sweep_kernel<NV, DIR, MODE, BATCH, SPEC_FE>), dim3((unsigned)g.ntiles),
-                       dim3(256), lds, s, a, b, g);
+    hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_FE, TM, W>), dim3((unsigned)g.ntiles),
+                       dim3(256), lds, s, a, b, g, mode);
   else
-    hipLaunchKernelGGL((sweep_kernel<NV, DIR, MODE, BATCH, SPEC_GENERIC>),
-                       dim3((unsigned)g.ntiles), dim3(256), lds, s, a, b, g);
+    hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_GENERIC, TM, W>),
+                       dim3((unsigned)g.ntiles), dim3(256), lds, s, a, b, g, mode);
   return hipGetLastError();
 }
 
 template <int NV, int DIR, bool BATCH>
-static hipError_t sweep_mode(int mode, const SweepArgs& a, const BatchArgs& b, const TileGeom& g,
-                             hipStream_t s) {
-  if (mode == MODE_RES) return sweep_go<NV, DIR, MODE_RES, BATCH>(a, b, g, s);
-  if (mode == MODE_ACC) return sweep_go<NV, DIR, MODE_ACC, BATCH>(a, b, g, s);
-  return sweep_go<NV, DIR, MODE_STAGE, BATCH>(a, b, g, s);
+static hipError_t sweep_shape(const SweepArgs& a, const BatchArgs& b, const TileGeom& g, int mode,
+                              hipStream_t s) {
+  if constexpr (DIR == 0) {
+    if (g.tm == 128) return sweep_go<NV, DIR, BATCH, 128, 1>(a, b, g, mode, s);
+    return sweep_go<NV, DIR, BATCH, 256, 1>(a, b, g, mode, s);
+  } else {
+    if (g.tm == 16) return sweep_go<NV, DIR, BATCH, 16, 8>(a, b, g, mode, s);
+    if (g.w == 4 && g.tm == 32) return sweep_go<NV, DIR, BATCH, 32, 4>(a, b, g, mode, s);
+    if (g.tm == 32) return sweep_go<NV, DIR, BATCH, 32, 8>(a, b, g, mode, s);
+    return sweep_go<NV, DIR, BATCH, 64, 4>(a, b, g, mode, s);
+  }
 }
 
 static TileGeom make_geom(int dir, const int64_t n[3], int diff, int tm, int w) {
   TileGeom g;
   g.tm = tm;
   g.w = w;
-  g.lw = ilog2(w);
-  g.ltmw = ilog2(tm * w);
+  g.lw = 0;
+  g.ltmw = 0;
   g.tl = tm - (diff ? 5 : 3);
   g.segs = ceil_div64(n[dir], g.tl);
   g.xgroups = dir == 0 ? 1 : ceil_div64(n[0], w);
@@ -299,7 +329,7 @@ hipError_t launch_sweep(int nv, int dir, const SweepArgs& a, int mode, int tm, i
   if (g.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
   BatchArgs b{};
 #define WCNS_S(NVV, DD) \
-  if (nv == NVV && dir == DD) return sweep_mode<NVV, DD, false>(mode, a, b, g, stream);
+  if (nv == NVV && dir == DD) return sweep_shape<NVV, DD, false>(a, b, g, mode, stream);
   WCNS_S(1, 0) WCNS_S(1, 1) WCNS_S(1, 2)
   WCNS_S(3, 0)
   WCNS_S(4, 0) WCNS_S(4, 1)
@@ -315,12 +345,12 @@ hipError_t launch_batch_sweep(const SweepArgs& a, const BatchArgs& b, int mode, 
   g.tm = tm;
   g.w = 1;
   g.lw = 0;
-  g.ltmw = ilog2(tm);
+  g.ltmw = 0;
   g.tl = tm - (a.diff ? 5 : 3);
   g.segs = 1;
   g.xgroups = 1;
   g.ntiles = b.ntiles;
-  return sweep_mode<3, 0, true>(mode, a, b, g, stream);
+  return sweep_shape<3, 0, true>(a, b, g, mode, stream);
 }
 
 }  // namespace wcns

@@ -9,9 +9,14 @@
 namespace wcns {
 
 __device__ __forceinline__ int64_t bc_index(int64_t j, int64_t N, int bc) {
-  if (bc == 0) {  // periodic
-    j %= N;
-    return j < 0 ? j + N : j;
+  if (bc == 0) {  // periodic: one wrap covers the ghosts; a general modulo otherwise
+    if (j < 0) j += N;
+    if (j >= N) j -= N;
+    if (j < 0 || j >= N) {
+      j %= N;
+      if (j < 0) j += N;
+    }
+    return j;
   }
   return j < 0 ? 0 : (j >= N ? N - 1 : j);  // transmissive: zeroth-order copy
 }
@@ -19,6 +24,13 @@ __device__ __forceinline__ int64_t bc_index(int64_t j, int64_t N, int bc) {
 __device__ __forceinline__ void flag_status(int32_t* status) {
   if (status) atomicOr(status, 1);
 }
+
+// Writes one node's result according to the sweep mode (MODE_RES, MODE_ACC
+// or MODE_STAGE; `mode` is uniform, so the switch costs a scalar branch).
+template <int NV>
+__device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gidx, int64_t vstride,
+                                        const double (&res)[NV], const double (&Un)[NV],
+                                        double dt);
 
 // Writes one node's result according to the sweep mode.  Un is the state
 // under the stencil at that node (needed by the stage combine).
@@ -46,6 +58,18 @@ __device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t v
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = y[v];
     if (!physical<NV>(y, a.pp.gamma)) flag_status(a.status);
   }
+}
+
+template <int NV>
+__device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gidx, int64_t vstride,
+                                        const double (&res)[NV], const double (&Un)[NV],
+                                        double dt) {
+  if (mode == MODE_RES)
+    emit<NV, MODE_RES>(a, gidx, vstride, res, Un, dt);
+  else if (mode == MODE_ACC)
+    emit<NV, MODE_ACC>(a, gidx, vstride, res, Un, dt);
+  else
+    emit<NV, MODE_STAGE>(a, gidx, vstride, res, Un, dt);
 }
 
 }  // namespace wcns
