@@ -5,6 +5,7 @@ The arithmetic runs in the hand-written HIP kernels of ``libwcns.so``
 (C ABI in ``include/wcns.h``); this package only marshals arguments and uses
 PyTorch for device memory and streams.  Importing it does not load the
 library; the first plan does, and fails loudly if it is not built.
+The differentiable checkpointed rollout lives in ``.rollout``.
 """
 __all__ = ["Plan", "BatchPlan", "WCNSError", "build"]
 

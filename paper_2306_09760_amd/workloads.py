@@ -186,16 +186,31 @@ def _fourier_density(g, n, nmodes=16, kmax=4, amp=0.2):
     return 1.0 + amp * S / np.max(np.abs(S))
 
 
-def adjoint2d(seed=0, n=1024, gamma=GAMMA):
+def adjoint2d(seed=0, n=1024, gamma=GAMMA, flow_amp=0.0):
     """Smooth periodic 2D Euler state on [0, 1)^2: rho0 = 1 + 0.2 * (sum of
     16 seeded Fourier modes, scaled to max |sum| = 1), u = v = 0.5, p = 1.
-    ``rho_target_init`` is the density of the same construction drawn with
-    seed + 1 (to be advanced by the same run to form the target)."""
-    rho0 = _fourier_density(rng(seed), n)
-    rho1 = _fourier_density(rng(seed + 1), n)
-    half = np.full((n, n), 0.5)
-    U = prim_to_cons(rho0, [half, half], np.ones((n, n)), gamma)
-    Ut = prim_to_cons(rho1, [half, half], np.ones((n, n)), gamma)
+    ``target_init`` is the same construction drawn with seed + 1 (to be
+    advanced by the same run to form the target).
+
+    With ``flow_amp`` > 0, u, v and p also vary: 0.5 + flow_amp * S_u,
+    0.5 + flow_amp * S_v and 1 + flow_amp * S_p, each S a sum of 16 modes
+    scaled to max |S| = 1 drawn from seeds seed + 10000 + (0, 1, 2) (seed + 1
+    + ... for the target), so that every characteristic field is resolved
+    well above rounding."""
+    def state(sd):
+        rho = _fourier_density(rng(sd), n)
+        if flow_amp > 0.0:
+            u = 0.5 + (_fourier_density(rng(sd + 10000), n, amp=flow_amp) - 1.0)
+            v = 0.5 + (_fourier_density(rng(sd + 10001), n, amp=flow_amp) - 1.0)
+            p = _fourier_density(rng(sd + 10002), n, amp=flow_amp)
+        else:
+            u = np.full((n, n), 0.5)
+            v = np.full((n, n), 0.5)
+            p = np.ones((n, n))
+        return prim_to_cons(rho, [u, v], p, gamma)
+
+    U = state(seed)
+    Ut = state(seed + 1)
     h = 1.0 / n
     prob = dict(system="euler", ndim=2, n=(n, n), h=(h, h), bc="periodic", gamma=gamma)
     return prob, np.ascontiguousarray(U), dict(target_init=np.ascontiguousarray(Ut))
