@@ -1,212 +1,426 @@
 // Adjoint (vector-Jacobian product) of the WCNS-FE residual on gfx950:
-// Ubar += scale * (dL/dU)^T Rbar, one direction at a time, in gather form.
+// Ubar += scale * (dL/dU)^T Rbar, one direction per launch.
 //
-//  adj_midpoint  one lane per midpoint: forms the midpoint-flux cotangent from
-//                Rbar (transpose of the flux difference), recomputes the
-//                forward midpoint flux and propagates the cotangent back to
-//                its six stencil nodes; the 6*NV contributions are stored in a
-//                midpoint-major buffer (variable-major, x fastest, so both
-//                writes and later reads are coalesced).
-//  adj_gather    one lane per node: sums the contributions of every (midpoint,
-//                stencil slot) that reads this node (ghost positions folded
-//                back through the boundary map) and the node-flux term of
-//                the midpoint-and-node difference.  No atomics: the result
-//                is deterministic.
+// A workgroup of 256 lanes owns the nodes i0 .. i0+TL-1 (TL = TM - 5) of W
+// adjacent lines and recomputes the TM midpoints i0-3 .. i0+TL+1 whose
+// fluxes read them, so every node's cotangent is completed inside one tile
+// (no atomics: the result is deterministic and independent of the launch
+// shape's scheduling).  Phases, separated by barriers:
+//   load     the TM+5 nodes of every column into LDS, ghosts applied;
+//   roe      Roe average per midpoint;
+//   interp   forward interpolation, one task per (side, field, midpoint);
+//   flux     per midpoint: flux cotangent from Rbar (transpose of the MND6 /
+//            MD6 difference), local Lax-Friedrichs VJP, back-projection VJP
+//            -> cotangents of the interpolated characteristic values and of
+//            the Roe quantities;
+//   interp^T one task per (field, midpoint): VJP of both interpolations of
+//            that field -> cotangents of the six projected stencil values;
+//   proj^T   per midpoint: projection VJP of the six stencil nodes (in place
+//            in LDS) and the Roe-average VJP onto the two centre nodes;
+//   gather   per node: the six midpoint contributions, ghost positions folded
+//            onto the boundary node (transmissive), the node-flux term of
+//            MND6, and Ubar += scale * sum.
+// LDS (doubles): sU[NV][TM+5][W] | sR[NR][TMW] | sRB[NR][TMW] | sW[2NV][TMW]
+// | sWB[6 NV][TMW], TMW = TM W.
 #include <hip/hip_runtime.h>
 
 #include "wcns_adjoint_device.hpp"
 #include "wcns_internal.hpp"
+#include "wcns_sweep_common.hpp"
 
 namespace wcns {
 
-struct AdjGeom {
-  int64_t n[3];      // node grid
-  int64_t nm[3];     // midpoint grid (n with n[dir] replaced by nmid)
-  int64_t Mtot;      // product of nm
-  int64_t N;         // n[dir]
-  int64_t mlo, mhi;  // midpoint range along dir (m + 1/2 between nodes m, m+1)
-  int64_t stride;    // node stride along dir
+template <int NV, int TM, int W>
+struct AdjLayout {
+  static constexpr int ND = NV > 1 ? NV - 2 : 1;
+  static constexpr int NR = NV > 1 ? NV - 2 + 6 : 0;
+  static constexpr int TN = TM + 5;
+  static constexpr int TMW = TM * W;
+  static constexpr int SV = TN * W;
+  static constexpr int LW = W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4;
+  static constexpr int LTMW = TMW == 64 ? 6 : TMW == 128 ? 7 : 8;
+  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(2 * NR + 8 * NV) * TMW;
+  static_assert(TMW == 64 || TMW == 128 || TMW == 256, "tile must hold 64, 128 or 256 midpoints");
+  static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
 
-__device__ __forceinline__ int64_t wrap_or_clamp(int64_t j, int64_t N, int bc) {
-  if (bc == 0) {
-    j %= N;
-    return j < 0 ? j + N : j;
-  }
-  return j < 0 ? 0 : (j >= N ? N - 1 : j);
-}
-
-// Rbar at position j along the line (0 outside a transmissive line).
+// Rbar at position j of a line (zero outside a transmissive line).
 __device__ __forceinline__ double rbar_at(const double* Rb, int64_t base, int64_t stride,
                                           int64_t j, int64_t N, int bc) {
-  if (bc == 0) return Rb[base + wrap_or_clamp(j, N, 0) * stride];
+  if (bc == 0) return Rb[base + bc_index(j, N, 0) * stride];
   if (j < 0 || j >= N) return 0.0;
   return Rb[base + j * stride];
 }
 
-template <int NV, int DIR, int SPEC>
-__global__ void __launch_bounds__(256) adj_midpoint_kernel(AdjArgs a, AdjGeom g) {
-  const int64_t lin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (lin >= g.Mtot) return;
-  int64_t c[3];
-  c[0] = lin % g.nm[0];
-  const int64_t rest = lin / g.nm[0];
-  c[1] = rest % g.nm[1];
-  c[2] = rest / g.nm[1];
-  const int64_t m = g.mlo + c[DIR];
-  c[DIR] = 0;
-  const int64_t base = c[0] + g.n[0] * (c[1] + g.n[1] * c[2]);
-  const int64_t N = g.N;
-  // Cotangent of the midpoint flux F~_{m+1/2} (transpose of the difference).
-  double Fb[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const double* Rb = a.Rbar + v * a.npts;
-    auto R = [&](int64_t j) { return rbar_at(Rb, base, g.stride, j, N, a.bc); };
-    double d;
-    if (a.diff == 0)
-      d = 1.5 * (R(m) - R(m + 1)) + (1.0 / 30.0) * (R(m - 1) - R(m + 2));
-    else
-      d = (75.0 / 64.0) * (R(m) - R(m + 1)) + (-25.0 / 384.0) * (R(m - 1) - R(m + 2)) +
-          (3.0 / 640.0) * (R(m - 2) - R(m + 3));
-    Fb[v] = -a.ih * d;
-  }
-  double s[6][NV], sb[6][NV];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    const int64_t idx = base + wrap_or_clamp(m - 2 + k, N, a.bc) * g.stride;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      s[k][v] = a.U[v * a.npts + idx];
-      sb[k][v] = 0.0;
+template <int NV, int DIR, int SPEC, int TM, int W>
+__global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
+  using L = AdjLayout<NV, TM, W>;
+  constexpr int ND = L::ND, NR = L::NR, TMW = L::TMW, SV = L::SV;
+  constexpr int LW = L::LW, LTMW = L::LTMW;
+  constexpr int NT = 256;
+  constexpr int TL = TM - 5;
+  extern __shared__ double smem[];
+  double* sU = smem;
+  double* sR = sU + NV * SV;
+  double* sRB = sR + NR * TMW;
+  double* sW = sRB + NR * TMW;
+  double* sWB = sW + 2 * NV * TMW;
+  const int tid = threadIdx.x;
+
+  const int64_t tile = blockIdx.x;
+  if (tile >= g.ntiles) return;
+  int64_t base, N, stride;
+  int ncol = 1;
+  const int64_t seg = tile % g.segs;
+  const int64_t r = tile / g.segs;
+  const int64_t i0 = seg * TL;
+  if constexpr (DIR == 0) {
+    N = a.n[0];
+    base = r * N;
+    stride = 1;
+  } else {
+    const int64_t xg = r % g.xgroups;
+    const int64_t other = r / g.xgroups;
+    const int64_t x0 = xg * W;
+    ncol = (int)((a.n[0] - x0) < W ? (a.n[0] - x0) : W);
+    if constexpr (DIR == 1) {
+      N = a.n[1];
+      stride = a.n[0];
+      base = x0 + other * a.n[0] * a.n[1];
+    } else {
+      N = a.n[2];
+      stride = a.n[0] * a.n[1];
+      base = x0 + other * a.n[0];
     }
   }
-  midpoint_flux_vjp<NV, DIR, SPEC>(a.ip, a.pp, s, Fb, sb);
-#pragma unroll
-  for (int k = 0; k < 6; ++k)
-#pragma unroll
-    for (int v = 0; v < NV; ++v) a.contrib[(k * NV + v) * g.Mtot + lin] = sb[k][v];
-}
+  const int64_t nb = i0 - 5;  // position of LDS node 0
 
-template <int NV, int DIR>
-__global__ void __launch_bounds__(256) adj_gather_kernel(AdjArgs a, AdjGeom g) {
-  const int64_t np = a.npts;
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= np) return;
-  int64_t c[3];
-  c[0] = node % g.n[0];
-  const int64_t rest = node / g.n[0];
-  c[1] = rest % g.n[1];
-  c[2] = rest / g.n[1];
-  const int64_t i = c[DIR];
-  const int64_t N = g.N;
-  int64_t cm[3] = {c[0], c[1], c[2]};
-  cm[DIR] = 0;
-  const int64_t mbase = cm[0] + g.nm[0] * (cm[1] + g.nm[1] * cm[2]);
-  const int64_t mstride = (DIR == 0) ? 1 : (DIR == 1 ? g.nm[0] : g.nm[0] * g.nm[1]);
-  const int G = a.diff ? 5 : 4;
+  // load
+  for (int idx = tid; idx < SV; idx += NT) {
+    const int k = idx >> LW, c = idx & (W - 1);
+    const int cc = c < ncol ? c : ncol - 1;
+    const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sU[v * SV + idx] = a.U[v * a.npts + gi];
+  }
+  __syncthreads();
 
-  double acc[NV];
+  const bool proj = (NV > 1) && a.pp.charproj;
+  if constexpr (NV > 1) {
+    if (proj) {
+#pragma unroll 1
+      for (int q = tid; q < TMW; q += NT) {
+        const double* u = sU + q + 2 * W;  // nodes m, m+1 of midpoint q
+        double UA[NV], UB[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  auto gather_pos = [&](int64_t pos) {
+        for (int v = 0; v < NV; ++v) {
+          UA[v] = u[v * SV];
+          UB[v] = u[v * SV + W];
+        }
+        const RoeState<ND> rs = roe_average<ND>(UA, UB, a.pp.gamma);
+        double* rr = sR + q;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const int64_t m = pos + 2 - k;
-      if (m >= g.mlo && m <= g.mhi) {
-        const int64_t l = mbase + (m - g.mlo) * mstride;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] += a.contrib[(k * NV + v) * g.Mtot + l];
+        for (int k = 0; k < ND; ++k) rr[k * TMW] = rs.vel[k];
+        rr[(ND + 0) * TMW] = rs.H;
+        rr[(ND + 1) * TMW] = rs.c;
+        rr[(ND + 2) * TMW] = rs.ic;
+        rr[(ND + 3) * TMW] = rs.q2h;
+        rr[(ND + 4) * TMW] = rs.b1;
+        rr[(ND + 5) * TMW] = rs.b2;
       }
+      __syncthreads();
+    }
+  }
+
+  auto load_roe = [&](int q) {
+    RoeState<ND> rs;
+    const double* rr = sR + q;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) rs.vel[k] = rr[k * TMW];
+    rs.H = rr[(ND + 0) * TMW];
+    rs.c = rr[(ND + 1) * TMW];
+    rs.ic = rr[(ND + 2) * TMW];
+    rs.q2h = rr[(ND + 3) * TMW];
+    rs.b1 = rr[(ND + 4) * TMW];
+    rs.b2 = rr[(ND + 5) * TMW];
+    return rs;
+  };
+  // the six (projected) stencil values of field v around midpoint rem
+  auto stencil = [&](int rem, int v, double (&w)[6]) {
+    const double* u = sU + rem;
+    if (proj) {
+      if constexpr (NV > 1) {
+        const RoeState<ND> rs = load_roe(rem);
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+          double U[NV];
+#pragma unroll
+          for (int e = 0; e < NV; ++e) U[e] = u[e * SV + s * W];
+          w[s] = project_field<ND, DIR>(rs, U, v);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) w[s] = u[v * SV + s * W];
     }
   };
-  gather_pos(i);
-  if (a.bc == 0) {
-    gather_pos(i - N);
-    gather_pos(i + N);
-  } else {
-    if (i == 0)
-      for (int q = 1; q <= G; ++q) gather_pos(-q);
-    if (i == N - 1)
-      for (int q = 0; q < G; ++q) gather_pos(N + q);
+
+  // forward interpolation, one task per (side, field, midpoint)
+#pragma unroll 1
+  for (int q = tid; q < 2 * NV * TMW; q += NT) {
+    const int slot = q >> LTMW;
+    const int rem = q & (TMW - 1);
+    const int side = slot >= NV;
+    const int v = side ? slot - NV : slot;
+    double w[6];
+    stencil(rem, v, w);
+    sW[q] = side ? interp5<SPEC>(a.ip, w[5], w[4], w[3], w[2], w[1])
+                 : interp5<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4]);
   }
-  if (a.diff == 0) {
-    // Node-flux term: F_j enters D_{j+1} with +3/10 and D_{j-1} with -3/10.
-    const int64_t base = node - i * g.stride;
-    double Fb[NV], U[NV], Ub[NV];
+  __syncthreads();
+
+  // flux VJP per midpoint: sW <- cotangents of the interpolated values
+#pragma unroll 1
+  for (int q = tid; q < TMW; q += NT) {
+    const int t = q >> LW, c = q & (W - 1);
+    const int cc = c < ncol ? c : ncol - 1;
+    const int64_t m = i0 - 3 + t;
+    const int64_t lb = base + cc;
+    double Fb[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double* Rb = a.Rbar + v * np;
-      auto R = [&](int64_t j) { return rbar_at(Rb, base, g.stride, j, N, a.bc); };
-      double f = -0.3 * a.ih * (R(i + 1) - R(i - 1));
-      if (a.bc != 0) {
-        if (i == 0) f += -0.3 * a.ih * (R(0) - R(-2));          // ghost node -1
-        if (i == N - 1) f += -0.3 * a.ih * (R(N + 1) - R(N - 1)); // ghost node N
+      const double* Rb = a.Rbar + v * a.npts;
+      const double r0 = rbar_at(Rb, lb, stride, m, N, a.bc);
+      const double r1 = rbar_at(Rb, lb, stride, m + 1, N, a.bc);
+      const double rm1 = rbar_at(Rb, lb, stride, m - 1, N, a.bc);
+      const double r2 = rbar_at(Rb, lb, stride, m + 2, N, a.bc);
+      double d;
+      if (a.diff == 0) {
+        d = 1.5 * (r0 - r1) + (1.0 / 30.0) * (rm1 - r2);
+      } else {
+        const double rm2 = rbar_at(Rb, lb, stride, m - 2, N, a.bc);
+        const double r3 = rbar_at(Rb, lb, stride, m + 3, N, a.bc);
+        d = (75.0 / 64.0) * (r0 - r1) + (-25.0 / 384.0) * (rm1 - r2) + (3.0 / 640.0) * (rm2 - r3);
       }
-      Fb[v] = f;
-      U[v] = a.U[v * np + node];
-      Ub[v] = 0.0;
+      Fb[v] = -a.ih * d;
     }
-    node_flux_vjp<NV, DIR>(a.pp, U, Fb, Ub);
+    if constexpr (NV == 1) {
+      sW[q] = 0.5 * (a.pp.adv + __builtin_fabs(a.pp.adv)) * Fb[0];
+      sW[TMW + q] = 0.5 * (a.pp.adv - __builtin_fabs(a.pp.adv)) * Fb[0];
+    } else {
+      double WL[NV], WR[NV], UL[NV], UR[NV], ULb[NV], URb[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += Ub[v];
+      for (int v = 0; v < NV; ++v) {
+        WL[v] = sW[v * TMW + q];
+        WR[v] = sW[(NV + v) * TMW + q];
+      }
+      if (proj) {
+        const RoeState<ND> rs = load_roe(q);
+        unproject<ND, DIR>(rs, WL, UL);
+        unproject<ND, DIR>(rs, WR, UR);
+        llf_vjp<ND, DIR>(UL, UR, a.pp.gamma, Fb, ULb, URb);
+        RoeBar<ND> rb;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) rb.vel[k] = 0.0;
+        rb.H = rb.c = rb.ic = rb.q2h = rb.b1 = rb.b2 = 0.0;
+        double WLb[NV], WRb[NV];
+        unproject_vjp<ND, DIR>(rs, WL, ULb, WLb, rb);
+        unproject_vjp<ND, DIR>(rs, WR, URb, WRb, rb);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          sW[v * TMW + q] = WLb[v];
+          sW[(NV + v) * TMW + q] = WRb[v];
+        }
+        double* rr = sRB + q;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) rr[k * TMW] = rb.vel[k];
+        rr[(ND + 0) * TMW] = rb.H;
+        rr[(ND + 1) * TMW] = rb.c;
+        rr[(ND + 2) * TMW] = rb.ic;
+        rr[(ND + 3) * TMW] = rb.q2h;
+        rr[(ND + 4) * TMW] = rb.b1;
+        rr[(ND + 5) * TMW] = rb.b2;
+      } else {
+        llf_vjp<ND, DIR>(WL, WR, a.pp.gamma, Fb, ULb, URb);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          sW[v * TMW + q] = ULb[v];
+          sW[(NV + v) * TMW + q] = URb[v];
+        }
+      }
+    }
   }
+  __syncthreads();
+
+  // interpolation VJP, one task per (field, midpoint): sWB[(j NV + v)] <- cotangent
+  // of stencil value j of field v
+#pragma unroll 1
+  for (int q = tid; q < NV * TMW; q += NT) {
+    const int v = q >> LTMW;
+    const int rem = q & (TMW - 1);
+    double w[6], wb[6];
+    stencil(rem, v, w);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) a.Ubar[v * np + node] += a.scale * acc[v];
+    for (int j = 0; j < 6; ++j) wb[j] = 0.0;
+    interp5_vjp<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4], sW[v * TMW + rem], wb[0], wb[1], wb[2],
+                      wb[3], wb[4]);
+    interp5_vjp<SPEC>(a.ip, w[5], w[4], w[3], w[2], w[1], sW[(NV + v) * TMW + rem], wb[5], wb[4],
+                      wb[3], wb[2], wb[1]);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sWB[(j * NV + v) * TMW + rem] = wb[j];
+  }
+  __syncthreads();
+
+  // projection and Roe-average VJP per midpoint (in place: slot j's NV rows)
+  if constexpr (NV > 1) {
+    if (proj) {
+#pragma unroll 1
+      for (int q = tid; q < TMW; q += NT) {
+        const RoeState<ND> rs = load_roe(q);
+        RoeBar<ND> rb;
+        const double* rr = sRB + q;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) rb.vel[k] = rr[k * TMW];
+        rb.H = rr[(ND + 0) * TMW];
+        rb.c = rr[(ND + 1) * TMW];
+        rb.ic = rr[(ND + 2) * TMW];
+        rb.q2h = rr[(ND + 3) * TMW];
+        rb.b1 = rr[(ND + 4) * TMW];
+        rb.b2 = rr[(ND + 5) * TMW];
+        const double* u = sU + q;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          double U[NV], Wb[NV], Ub[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            U[v] = u[v * SV + j * W];
+            Wb[v] = sWB[(j * NV + v) * TMW + q];
+            Ub[v] = 0.0;
+          }
+          project_vjp<ND, DIR>(rs, U, Wb, Ub, rb);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sWB[(j * NV + v) * TMW + q] = Ub[v];
+        }
+        double UA[NV], UB[NV], UbA[NV], UbB[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          UA[v] = u[v * SV + 2 * W];
+          UB[v] = u[v * SV + 3 * W];
+          UbA[v] = 0.0;
+          UbB[v] = 0.0;
+        }
+        roe_vjp<ND>(UA, UB, a.pp.gamma, rs, rb, UbA, UbB);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          sWB[(2 * NV + v) * TMW + q] += UbA[v];
+          sWB[(3 * NV + v) * TMW + q] += UbB[v];
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // gather per node
+  const int G = a.diff ? 5 : 4;
+#pragma unroll 1
+  for (int q = tid; q < TL * W; q += NT) {
+    const int t = q >> LW, c = q & (W - 1);
+    const int64_t i = i0 + t;
+    if (i >= N || c >= ncol) continue;
+    const int k = t + 5;  // LDS node index of node i
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    // contributions at LDS position kk: midpoints kk - j, j = 0..5, inside the tile
+    auto add_position = [&](int kk) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        const int tm = kk - j;
+        if (tm >= 0 && tm < TM) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) acc[v] += sWB[(j * NV + v) * TMW + tm * W + c];
+        }
+      }
+    };
+    add_position(k);
+    if (a.bc != 0) {
+      if (i == 0)
+        for (int gg = 1; gg <= G; ++gg) add_position(k - gg);
+      if (i == N - 1)
+        for (int gg = 1; gg <= G; ++gg) add_position(k + gg);
+    }
+    if (a.diff == 0) {
+      // node flux F_i enters D_{i+1} with -3/10 and D_{i-1} with +3/10
+      const int64_t lb = base + c;
+      double Fb[NV], U[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double* Rb = a.Rbar + v * a.npts;
+        double f = -0.3 * a.ih *
+                   (rbar_at(Rb, lb, stride, i + 1, N, a.bc) - rbar_at(Rb, lb, stride, i - 1, N, a.bc));
+        if (a.bc != 0) {
+          if (i == 0)  // ghost node -1 carries U_0
+            f += -0.3 * a.ih * rbar_at(Rb, lb, stride, 0, N, a.bc);
+          if (i == N - 1)  // ghost node N carries U_{N-1}
+            f += 0.3 * a.ih * rbar_at(Rb, lb, stride, N - 1, N, a.bc);
+        }
+        Fb[v] = f;
+        U[v] = sU[v * SV + k * W + c];
+      }
+      node_flux_vjp<NV, DIR>(a.pp, U, Fb, acc);
+    }
+    const int64_t gidx = base + i * stride + c;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.Ubar[v * a.npts + gidx] += a.scale * acc[v];
+  }
 }
 
-static AdjGeom make_geom(int dir, const int64_t n[3], int diff, int bc) {
-  AdjGeom g;
-  for (int k = 0; k < 3; ++k) {
-    g.n[k] = n[k];
-    g.nm[k] = n[k];
-  }
-  g.N = n[dir];
-  if (bc == 0) {
-    g.mlo = 0;
-    g.mhi = g.N - 1;
-  } else {
-    g.mlo = diff ? -3 : -2;
-    g.mhi = diff ? g.N + 1 : g.N;
-  }
-  g.nm[dir] = g.mhi - g.mlo + 1;
-  g.Mtot = g.nm[0] * g.nm[1] * g.nm[2];
-  g.stride = (dir == 0) ? 1 : (dir == 1 ? n[0] : n[0] * n[1]);
-  return g;
-}
+// --------------------------------------------------------------- launchers --
+static inline int64_t ceil_div64(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
-size_t adjoint_contrib_elems(int nv, int dir, const int64_t n[3], int diff) {
-  AdjGeom g = make_geom(dir, n, diff, 1);
-  return (size_t)6 * nv * g.Mtot;
-}
+// Tile shape per variable count: 128 midpoints per tile while the LDS stays
+// within 64 KB, 64 for the 3D Euler system.
+template <int NV, int DIR>
+struct AdjShape {
+  static constexpr int TMW = NV == 5 ? 64 : 128;
+  static constexpr int W = DIR == 0 ? 1 : 4;
+  static constexpr int TM = TMW / W;
+};
 
 template <int NV, int DIR>
 static hipError_t adj_go(const AdjArgs& a, hipStream_t s) {
-  const AdjGeom g = make_geom(DIR, a.n, a.diff, a.bc);
-  const int64_t b1 = (g.Mtot + 255) / 256;
+  constexpr int TM = AdjShape<NV, DIR>::TM, W = AdjShape<NV, DIR>::W;
+  using L = AdjLayout<NV, TM, W>;
+  static_assert(L::lds_doubles * sizeof(double) <= 64 * 1024, "adjoint tile exceeds 64 KB of LDS");
+  TileGeom g;
+  g.tm = TM;
+  g.w = W;
+  g.lw = L::LW;
+  g.ltmw = L::LTMW;
+  g.tl = TM - 5;
+  g.segs = ceil_div64(a.n[DIR], g.tl);
+  g.xgroups = DIR == 0 ? 1 : ceil_div64(a.n[0], W);
+  const int64_t others = DIR == 0 ? a.n[1] * a.n[2] : (DIR == 1 ? a.n[2] : a.n[1]);
+  g.ntiles = g.segs * g.xgroups * others;
+  if (g.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+  const size_t lds = sizeof(double) * L::lds_doubles;
   if (spec_of(a.ip) == SPEC_FE)
-    hipLaunchKernelGGL((adj_midpoint_kernel<NV, DIR, SPEC_FE>), dim3((unsigned)b1), dim3(256), 0, s,
-                       a, g);
+    hipLaunchKernelGGL((adj_sweep_kernel<NV, DIR, SPEC_FE, TM, W>), dim3((unsigned)g.ntiles),
+                       dim3(256), lds, s, a, g);
   else
-    hipLaunchKernelGGL((adj_midpoint_kernel<NV, DIR, SPEC_GENERIC>), dim3((unsigned)b1), dim3(256),
-                       0, s, a, g);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int64_t b2 = (a.npts + 255) / 256;
-  hipLaunchKernelGGL((adj_gather_kernel<NV, DIR>), dim3((unsigned)b2), dim3(256), 0, s, a, g);
+    hipLaunchKernelGGL((adj_sweep_kernel<NV, DIR, SPEC_GENERIC, TM, W>), dim3((unsigned)g.ntiles),
+                       dim3(256), lds, s, a, g);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint_dir(int nv, int dir, const AdjArgs& a, hipStream_t stream) {
-  if (nv == 1 && dir == 0) return adj_go<1, 0>(a, stream);
-  if (nv == 1 && dir == 1) return adj_go<1, 1>(a, stream);
-  if (nv == 1 && dir == 2) return adj_go<1, 2>(a, stream);
-  if (nv == 3 && dir == 0) return adj_go<3, 0>(a, stream);
-  if (nv == 4 && dir == 0) return adj_go<4, 0>(a, stream);
-  if (nv == 4 && dir == 1) return adj_go<4, 1>(a, stream);
-  if (nv == 5 && dir == 0) return adj_go<5, 0>(a, stream);
-  if (nv == 5 && dir == 1) return adj_go<5, 1>(a, stream);
-  if (nv == 5 && dir == 2) return adj_go<5, 2>(a, stream);
+#define WCNS_A(NVV, DD) \
+  if (nv == NVV && dir == DD) return adj_go<NVV, DD>(a, stream);
+  WCNS_A(1, 0) WCNS_A(1, 1) WCNS_A(1, 2)
+  WCNS_A(3, 0)
+  WCNS_A(4, 0) WCNS_A(4, 1)
+  WCNS_A(5, 0) WCNS_A(5, 1) WCNS_A(5, 2)
+#undef WCNS_A
   return hipErrorInvalidValue;
 }
 

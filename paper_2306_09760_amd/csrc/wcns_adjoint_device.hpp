@@ -272,163 +272,101 @@ __device__ __forceinline__ void roe_vjp(const double* UA, const double* UB, doub
   node(UB, B, sB, sBb, HBb, velBb, UbB);
 }
 
-// VJP of the midpoint flux: given Fb (NV), accumulate sb[0..5][NV] (must be
-// zeroed by the caller) = (dF/ds)^T Fb.
-template <int NV, int DIR, int SPEC = SPEC_GENERIC>
-__device__ __forceinline__ void midpoint_flux_vjp(const InterpParams& IP, const PhysParams& PP,
-                                                  const double (&s)[6][NV], const double (&Fb)[NV],
-                                                  double (&sb)[6][NV]) {
-  if constexpr (NV == 1) {
-    const double ubL = 0.5 * (PP.adv + __builtin_fabs(PP.adv)) * Fb[0];
-    const double ubR = 0.5 * (PP.adv - __builtin_fabs(PP.adv)) * Fb[0];
-    interp5_vjp<SPEC>(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], ubL, sb[0][0], sb[1][0], sb[2][0],
-                sb[3][0], sb[4][0]);
-    interp5_vjp<SPEC>(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0], ubR, sb[5][0], sb[4][0], sb[3][0],
-                sb[2][0], sb[1][0]);
-  } else {
-    constexpr int ND = NV - 2;
-    const double gamma = PP.gamma;
-    double UL[NV], UR[NV], WL[NV], WR[NV];
-    RoeState<ND> r;
-    if (PP.charproj) {
-      r = roe_average<ND>(s[2], s[3], gamma);
-      double W[6][NV];
+// Local Lax-Friedrichs flux F = (F(UL) + F(UR)) / 2 - alpha (UR - UL) / 2,
+// alpha = max(lam(UL), lam(UR)): sets ULb, URb = (dF/dUL)^T Fb, (dF/dUR)^T Fb.
+template <int ND, int DIR>
+__device__ __forceinline__ void llf_vjp(const double* UL, const double* UR, double gamma,
+                                        const double* Fb, double* ULb, double* URb) {
+  constexpr int NV = ND + 2;
+  const Prim<ND> L = primitives<ND>(UL, gamma);
+  const Prim<ND> R = primitives<ND>(UR, gamma);
+  const double lamL = __builtin_fabs(L.vel[DIR]) + __builtin_sqrt(gamma * L.p * L.ir);
+  const double lamR = __builtin_fabs(R.vel[DIR]) + __builtin_sqrt(gamma * R.p * R.ir);
+  const bool takeL = lamL >= lamR;
+  const double alpha = takeL ? lamL : lamR;
+  double alphab = 0.0, Fh[NV];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) project<ND, DIR>(r, s[j], W[j]);
+  for (int v = 0; v < NV; ++v) {
+    alphab += -0.5 * (UR[v] - UL[v]) * Fb[v];
+    ULb[v] = 0.5 * alpha * Fb[v];
+    URb[v] = -0.5 * alpha * Fb[v];
+    Fh[v] = 0.5 * Fb[v];
+  }
+  flux_speed_vjp<ND, DIR>(UL, gamma, Fh, takeL ? alphab : 0.0, ULb);
+  flux_speed_vjp<ND, DIR>(UR, gamma, Fh, takeL ? 0.0 : alphab, URb);
+}
+
+// Back-projection U = R W (see unproject): sets Wb = R^T Ub and accumulates
+// the cotangent of the Roe quantities R depends on into rb.
+template <int ND, int DIR>
+__device__ __forceinline__ void unproject_vjp(const RoeState<ND>& r, const double* W,
+                                              const double* Ub, double* Wb, RoeBar<ND>& rb) {
+  constexpr int NV = ND + 2;
+  const double sum = W[0] + W[1] + W[ND + 1];
+  const double dif = W[ND + 1] - W[0];
+  double sumb = Ub[0], difb = 0.0;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        WL[v] = interp5<SPEC>(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
-        WR[v] = interp5<SPEC>(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
-      }
-      unproject<ND, DIR>(r, WL, UL);
-      unproject<ND, DIR>(r, WR, UR);
-    } else {
+  for (int v = 0; v < NV; ++v) Wb[v] = 0.0;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        UL[v] = interp5<SPEC>(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
-        UR[v] = interp5<SPEC>(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
-      }
-    }
-    // LLF
-    double ULb[NV], URb[NV];
-    {
-      const Prim<ND> L = primitives<ND>(UL, gamma);
-      const Prim<ND> R = primitives<ND>(UR, gamma);
-      const double lamL = __builtin_fabs(L.vel[DIR]) + __builtin_sqrt(gamma * L.p * L.ir);
-      const double lamR = __builtin_fabs(R.vel[DIR]) + __builtin_sqrt(gamma * R.p * R.ir);
-      const bool takeL = lamL >= lamR;
-      const double alpha = takeL ? lamL : lamR;
-      double alphab = 0.0, Fh[NV];
+  for (int k = 0; k < ND; ++k) {
+    rb.vel[k] += Ub[1 + k] * sum;
+    sumb += Ub[1 + k] * r.vel[k];
+  }
+  rb.c += Ub[1 + DIR] * dif;
+  difb += Ub[1 + DIR] * r.c;
+  const double Eb = Ub[ND + 1];
+  rb.H += Eb * (W[0] + W[ND + 1]);
+  Wb[0] += Eb * r.H;
+  Wb[ND + 1] += Eb * r.H;
+  rb.vel[DIR] += Eb * r.c * dif;
+  rb.c += Eb * r.vel[DIR] * dif;
+  difb += Eb * r.vel[DIR] * r.c;
+  rb.q2h += Eb * W[1];
+  Wb[1] += Eb * r.q2h;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        alphab += -0.5 * (UR[v] - UL[v]) * Fb[v];
-        ULb[v] = 0.5 * alpha * Fb[v];
-        URb[v] = -0.5 * alpha * Fb[v];
-        Fh[v] = 0.5 * Fb[v];
-      }
-      flux_speed_vjp<ND, DIR>(UL, gamma, Fh, takeL ? alphab : 0.0, ULb);
-      flux_speed_vjp<ND, DIR>(UR, gamma, Fh, takeL ? 0.0 : alphab, URb);
-    }
-    if (!PP.charproj) {
+  for (int t = 0; t < ND - 1; ++t) {
+    const int ax = tangential_axis<ND, DIR>(t);
+    Wb[2 + t] += Ub[1 + ax] + Eb * r.vel[ax];
+    rb.vel[ax] += Eb * W[2 + t];
+  }
+  Wb[0] += sumb - difb;
+  Wb[1] += sumb;
+  Wb[ND + 1] += sumb + difb;
+}
+
+// Projection W = L U of one node (see project): accumulates Ub += L^T Wb
+// and the cotangent of the Roe quantities L depends on into rb.
+template <int ND, int DIR>
+__device__ __forceinline__ void project_vjp(const RoeState<ND>& r, const double* U,
+                                            const double* Wb, double* Ub, RoeBar<ND>& rb) {
+  double um = 0.0;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        interp5_vjp<SPEC>(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ULb[v], sb[0][v], sb[1][v],
-                    sb[2][v], sb[3][v], sb[4][v]);
-        interp5_vjp<SPEC>(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v], URb[v], sb[5][v], sb[4][v],
-                    sb[3][v], sb[2][v], sb[1][v]);
-      }
-      return;
-    }
-    RoeBar<ND> rb;
+  for (int k = 0; k < ND; ++k) um += r.vel[k] * U[1 + k];
+  const double thb = 0.5 * Wb[0] - Wb[1] + 0.5 * Wb[ND + 1];
+  const double anb = 0.5 * Wb[0] - 0.5 * Wb[ND + 1];
+  Ub[0] += Wb[1];
 #pragma unroll
-    for (int k = 0; k < ND; ++k) rb.vel[k] = 0.0;
-    rb.H = rb.c = rb.ic = rb.q2h = rb.b1 = rb.b2 = 0.0;
-    // Back-projection U = R W for both sides.
-    double WLb[NV], WRb[NV];
-    auto unproj_vjp = [&](const double* W, const double* Ub, double* Wb) {
-      const double sum = W[0] + W[1] + W[ND + 1];
-      const double dif = W[ND + 1] - W[0];
-      double sumb = Ub[0], difb = 0.0;
+  for (int t = 0; t < ND - 1; ++t) {
+    const int ax = tangential_axis<ND, DIR>(t);
+    Ub[1 + ax] += Wb[2 + t];
+    rb.vel[ax] -= Wb[2 + t] * U[0];
+    Ub[0] -= Wb[2 + t] * r.vel[ax];
+  }
+  // an = (vel_n rho - m_n) ic
+  rb.vel[DIR] += anb * U[0] * r.ic;
+  Ub[0] += anb * r.vel[DIR] * r.ic;
+  Ub[1 + DIR] -= anb * r.ic;
+  rb.ic += anb * (r.vel[DIR] * U[0] - U[1 + DIR]);
+  // theta = b2 rho - b1 um + b1 E
+  rb.b2 += thb * U[0];
+  Ub[0] += thb * r.b2;
+  rb.b1 += thb * (U[ND + 1] - um);
+  Ub[ND + 1] += thb * r.b1;
+  const double umb = -thb * r.b1;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Wb[v] = 0.0;
-#pragma unroll
-      for (int k = 0; k < ND; ++k) {
-        rb.vel[k] += Ub[1 + k] * sum;
-        sumb += Ub[1 + k] * r.vel[k];
-      }
-      rb.c += Ub[1 + DIR] * dif;
-      difb += Ub[1 + DIR] * r.c;
-      const double Eb = Ub[ND + 1];
-      rb.H += Eb * (W[0] + W[ND + 1]);
-      Wb[0] += Eb * r.H;
-      Wb[ND + 1] += Eb * r.H;
-      rb.vel[DIR] += Eb * r.c * dif;
-      rb.c += Eb * r.vel[DIR] * dif;
-      difb += Eb * r.vel[DIR] * r.c;
-      rb.q2h += Eb * W[1];
-      Wb[1] += Eb * r.q2h;
-#pragma unroll
-      for (int t = 0; t < ND - 1; ++t) {
-        const int ax = tangential_axis<ND, DIR>(t);
-        Wb[2 + t] += Ub[1 + ax] + Eb * r.vel[ax];
-        rb.vel[ax] += Eb * W[2 + t];
-      }
-      Wb[0] += sumb - difb;
-      Wb[1] += sumb;
-      Wb[ND + 1] += sumb + difb;
-    };
-    unproj_vjp(WL, ULb, WLb);
-    unproj_vjp(WR, URb, WRb);
-    // Interpolation: cotangents of the projected stencil values.
-    double Wst[6][NV], Wb[6][NV];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      project<ND, DIR>(r, s[j], Wst[j]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) Wb[j][v] = 0.0;
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      interp5_vjp<SPEC>(IP, Wst[0][v], Wst[1][v], Wst[2][v], Wst[3][v], Wst[4][v], WLb[v], Wb[0][v],
-                  Wb[1][v], Wb[2][v], Wb[3][v], Wb[4][v]);
-      interp5_vjp<SPEC>(IP, Wst[5][v], Wst[4][v], Wst[3][v], Wst[2][v], Wst[1][v], WRb[v], Wb[5][v],
-                  Wb[4][v], Wb[3][v], Wb[2][v], Wb[1][v]);
-    }
-    // Projection W_j = L U_j.
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const double* U = s[j];
-      double um = 0.0;
-#pragma unroll
-      for (int k = 0; k < ND; ++k) um += r.vel[k] * U[1 + k];
-      const double thb = 0.5 * Wb[j][0] - Wb[j][1] + 0.5 * Wb[j][ND + 1];
-      const double anb = 0.5 * Wb[j][0] - 0.5 * Wb[j][ND + 1];
-      sb[j][0] += Wb[j][1];
-#pragma unroll
-      for (int t = 0; t < ND - 1; ++t) {
-        const int ax = tangential_axis<ND, DIR>(t);
-        sb[j][1 + ax] += Wb[j][2 + t];
-        rb.vel[ax] -= Wb[j][2 + t] * U[0];
-        sb[j][0] -= Wb[j][2 + t] * r.vel[ax];
-      }
-      // an = (vel_n rho - m_n) ic
-      rb.vel[DIR] += anb * U[0] * r.ic;
-      sb[j][0] += anb * r.vel[DIR] * r.ic;
-      sb[j][1 + DIR] -= anb * r.ic;
-      rb.ic += anb * (r.vel[DIR] * U[0] - U[1 + DIR]);
-      // theta = b2 rho - b1 um + b1 E
-      rb.b2 += thb * U[0];
-      sb[j][0] += thb * r.b2;
-      rb.b1 += thb * (U[ND + 1] - um);
-      sb[j][ND + 1] += thb * r.b1;
-      const double umb = -thb * r.b1;
-#pragma unroll
-      for (int k = 0; k < ND; ++k) {
-        rb.vel[k] += umb * U[1 + k];
-        sb[j][1 + k] += umb * r.vel[k];
-      }
-    }
-    roe_vjp<ND>(s[2], s[3], gamma, r, rb, sb[2], sb[3]);
+  for (int k = 0; k < ND; ++k) {
+    rb.vel[k] += umb * U[1 + k];
+    Ub[1 + k] += umb * r.vel[k];
   }
 }
 

@@ -171,8 +171,7 @@ struct wcns_plan {
   InterpParams ip;
   double ih[3];
   int ncfl;
-  size_t off_W1, off_W2, off_R, off_partial, off_dt, off_A1, off_A2, off_A3, off_C, bytes;
-  size_t contrib_elems;
+  size_t off_W1, off_W2, off_R, off_partial, off_dt, off_A1, off_A2, off_A3, bytes;
 };
 
 struct wcns_batch_plan {
@@ -313,10 +312,6 @@ wcns_status wcns_plan_create(const wcns_desc* desc, wcns_plan** plan) {
   }
   P->ncfl = cfl_blocks(P->npts);
   const size_t state = sizeof(double) * P->nv * P->npts;
-  size_t contrib = 0;
-  for (int d = 0; d < desc->ndim; ++d)
-    contrib = std::max(contrib, adjoint_contrib_elems(P->nv, d, desc->n, desc->diff));
-  P->contrib_elems = contrib;
   size_t o = 0;
   P->off_W1 = o; o += align256(state);
   P->off_W2 = o; o += align256(state);
@@ -324,7 +319,6 @@ wcns_status wcns_plan_create(const wcns_desc* desc, wcns_plan** plan) {
   P->off_A1 = o; o += align256(state);
   P->off_A2 = o; o += align256(state);
   P->off_A3 = o; o += align256(state);
-  P->off_C = o; o += align256(sizeof(double) * contrib);
   P->off_partial = o; o += align256(sizeof(double) * P->ncfl);
   P->off_dt = o; o += 256;
   P->bytes = o;
@@ -414,13 +408,11 @@ wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double
   g_err.clear();
   if (!plan || !U || !Rbar || !Ubar || !work) return fail(WCNS_EINVAL, "NULL argument");
   if (Ubar == U || Ubar == Rbar) return fail(WCNS_EINVAL, "Ubar must not alias U or Rbar");
-  char* w = (char*)work;
   for (int d = 0; d < plan->d.ndim; ++d) {
     AdjArgs a;
     std::memset(&a, 0, sizeof a);
     a.U = U;
     a.Rbar = Rbar;
-    a.contrib = (double*)(w + plan->off_C);
     a.Ubar = Ubar;
     a.scale = 1.0;
     a.npts = plan->npts;

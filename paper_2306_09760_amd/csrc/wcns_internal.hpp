@@ -77,7 +77,6 @@ hipError_t launch_zero(double* y, int64_t n, hipStream_t stream);
 struct AdjArgs {
   const double* U;      // state
   const double* Rbar;   // cotangent of the residual
-  double* contrib;      // per-midpoint contributions: [(m * 6 + k) * NV + v] blocks
   double* Ubar;         // accumulated cotangent of U
   double scale;         // Ubar += scale * (dL/dU)^T Rbar
   int64_t npts;
@@ -89,7 +88,6 @@ struct AdjArgs {
   PhysParams pp;
 };
 hipError_t launch_adjoint_dir(int nv, int dir, const AdjArgs& a, hipStream_t stream);
-size_t adjoint_contrib_elems(int nv, int dir, const int64_t n[3], int diff);
 
 int cfl_blocks(int64_t npts);
 
