@@ -149,10 +149,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- adjoint / forward step time on the 2D periodic problem ----------
+    # ---- adjoint / forward time on the 2D periodic problem ----------------
     adjoint = None
     if not args.no_adjoint:
-        prob5, U5, _ = W.adjoint2d(seed=args.seed, n=1024)
+        from paper_2306_09760_amd import rollout as RO
+        prob5, U5, _ = W.adjoint2d(seed=args.seed, n=1024, flow_amp=0.05)
         P5 = Plan(**prob5, weights=args.weights, xi=args.xi)
         U5d = torch.from_numpy(U5).to(dev)
         P5.autotune(U5d)
@@ -176,10 +177,38 @@ def main():
         a1.record()
         torch.cuda.synchronize()
         adj_ms = a0.elapsed_time(a1) / reps
-        adjoint = {"workload": "2D Euler periodic 1024^2, smooth density, FE xi=%g" % args.xi,
+
+        # 100-step differentiable rollout of J = 1/2 ||rho(T)||^2-type loss:
+        # forward, then backward with every state stored (no recompute) and
+        # with 9 checkpoints besides U0 (binomial recompute)
+        nsteps = 100
+
+        def roll(snap):
+            X = U5d.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            UT = RO.rollout(P5, X, dt5, nsteps, snap)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            UT[0].sum().backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            return (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+        roll(nsteps - 1)  # warm
+        f_all, b_all = roll(nsteps - 1)
+        f_rev, b_rev = roll(9)
+        adjoint = {"workload": "2D Euler periodic 1024^2, smooth rho, u, v, p, FE xi=%g" % args.xi,
                    "forward_step_ms": round(fwd_ms, 4), "adjoint_step_ms": round(adj_ms, 4),
                    "ratio": round(adj_ms / fwd_ms, 3),
-                   "note": "adjoint step includes recomputing the two stage states"}
+                   "rollout_steps": nsteps,
+                   "rollout_forward_ms": round(f_all, 2),
+                   "rollout_backward_ms_all_states_stored": round(b_all, 2),
+                   "rollout_backward_ms_9_checkpoints": round(b_rev, 2),
+                   "recomputed_steps_9_checkpoints": RO.schedule_cost(nsteps, 9),
+                   "ratio_rollout_no_recompute": round(b_all / f_all, 3),
+                   "ratio_rollout_with_recompute": round(b_rev / f_rev, 3),
+                   "note": "adjoint step recomputes its two stage states"}
 
     # ---- CPU oracle on a bounded sample ----------------------------------
     cpu = None

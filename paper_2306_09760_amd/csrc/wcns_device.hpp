@@ -153,23 +153,68 @@ __device__ __forceinline__ double fe_map(double w, const double (&a)[NT], const 
   return g;
 }
 
+// A_j = a_j + b_j w of the three maps.
+constexpr double kG0a[3] = {0.5 * D0, 0.5 * (1.0 / 6.0 - D0), -0.5 / 6.0};
+constexpr double kG0b[3] = {-0.5, 0.0, 0.5};
+constexpr double kG1a[4] = {0.5 * D1, 0.5 * (0.5 - D1), 0.5 * (5.0 / 6.0 - 0.5), -0.5 * 5.0 / 6.0};
+constexpr double kG1b[4] = {-0.5, 0.0, 0.0, 0.5};
+constexpr double kG2a[3] = {0.5 * D2, 0.5 * (0.5 - D2), -0.25};
+constexpr double kG2b[3] = {-0.5, 0.0, 0.5};
+
 template <int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ double fe_g0(double w, const InterpParams& P, double* dg = nullptr) {
-  constexpr double a[3] = {0.5 * D0, 0.5 * (1.0 / 6.0 - D0), -0.5 / 6.0};
-  constexpr double b[3] = {-0.5, 0.0, 0.5};
-  return fe_map<3, SPEC>(w, a, b, P.K, P.C2[0], P, dg);
+  return fe_map<3, SPEC>(w, kG0a, kG0b, P.K, P.C2[0], P, dg);
 }
 template <int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ double fe_g1(double w, const InterpParams& P, double* dg = nullptr) {
-  constexpr double a[4] = {0.5 * D1, 0.5 * (0.5 - D1), 0.5 * (5.0 / 6.0 - 0.5), -0.5 * 5.0 / 6.0};
-  constexpr double b[4] = {-0.5, 0.0, 0.0, 0.5};
-  return fe_map<4, SPEC>(w, a, b, P.K + 3, P.C2[1], P, dg);
+  return fe_map<4, SPEC>(w, kG1a, kG1b, P.K + 3, P.C2[1], P, dg);
 }
 template <int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double* dg = nullptr) {
-  constexpr double a[3] = {0.5 * D2, 0.5 * (0.5 - D2), -0.25};
-  constexpr double b[3] = {-0.5, 0.0, 0.5};
-  return fe_map<3, SPEC>(w, a, b, P.K + 7, P.C2[2], P, dg);
+  return fe_map<3, SPEC>(w, kG2a, kG2b, P.K + 7, P.C2[2], P, dg);
+}
+
+// g(w) of one map in the form used by the forward SPEC_FE path.  With
+// t_j = tanh(xi (w - nu_j)) = 1 - 2 / D_j, D_j = 1 + q_j, q_j = E K_j:
+//   g(w) = w + sum_j A_j(w) - 2 sum_j A_j(w) / D_j,
+// and the last sum is taken over the common denominator prod_j D_j, so the
+// map costs one reciprocal instead of one per term.  q_j is clamped to
+// [e^-45, e^45]: at either end the term contributes exactly what t_j = -1 or
+// +1 does (A_j / D_j rounds away against the other terms, or D_j rounds to 1),
+// and the products of up to four D_j stay below e^180.
+template <int NT>
+__device__ __forceinline__ double fe_map_fast(double w, const double (&a)[NT],
+                                              const double (&b)[NT], const double* K, double C2,
+                                              double xi2) {
+  static_assert(NT == 3 || NT == 4, "maps have three or four terms");
+  constexpr double kQlo = 2.8625185805493937e-20;  // e^-45
+  constexpr double kQhi = 3.4934271057485095e+19;  // e^45
+  double sa = 0.0, sb = 1.0;
+  for (int j = 0; j < NT; ++j) {
+    sa += a[j];
+    sb += b[j];
+  }
+  const double E = exp_cw(__builtin_fma(xi2, w, -C2));
+  double D[NT], A[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    const double q = __builtin_fmin(__builtin_fmax(E * K[j], kQlo), kQhi);
+    D[j] = q + 1.0;
+    A[j] = __builtin_fma(b[j], w, a[j]);
+  }
+  double num, den;
+  const double d01 = D[0] * D[1];
+  const double n01 = __builtin_fma(A[0], D[1], A[1] * D[0]);
+  if constexpr (NT == 3) {
+    num = __builtin_fma(n01, D[2], A[2] * d01);
+    den = d01 * D[2];
+  } else {
+    const double d23 = D[2] * D[3];
+    const double n23 = __builtin_fma(A[2], D[3], A[3] * D[2]);
+    num = __builtin_fma(n01, d23, n23 * d01);
+    den = d01 * d23;
+  }
+  return __builtin_fma(-2.0 * num, rcp(den), __builtin_fma(sb, w, sa));
 }
 
 // Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
@@ -198,6 +243,26 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
   const double IS1 = f1 * f1 + s1 * s1;
   const double IS2 = f2 * f2 + s2 * s2;
 
+  if constexpr (FE) {
+    // Z weights (p = 2) over the common denominator: alpha_k (IS_0 + eps)^2
+    // (IS_1 + eps)^2 (IS_2 + eps)^2 = d_k ((IS_k + eps)^2 + tau^2) times the
+    // other two squares; one reciprocal normalises them.  The smallest
+    // product, eps^6 = 1e-240, is still a normal number.
+    const double tau = __builtin_fabs(IS0 - IS2);
+    const double t2 = tau * tau;
+    const double b0 = IS0 + P.eps, b1 = IS1 + P.eps, b2 = IS2 + P.eps;
+    const double q0 = b0 * b0, q1 = b1 * b1, q2 = b2 * b2;
+    const double z0 = D0 * (q0 + t2) * (q1 * q2);
+    const double z1 = D1 * (q1 + t2) * (q0 * q2);
+    const double z2 = D2 * (q2 + t2) * (q0 * q1);
+    const double zi = rcp(z0 + z1 + z2);
+    const double xi2 = 2.0 * P.xi;
+    const double g0 = fe_map_fast<3>(z0 * zi, kG0a, kG0b, P.K, P.C2[0], xi2);
+    const double g1 = fe_map_fast<4>(z1 * zi, kG1a, kG1b, P.K + 3, P.C2[1], xi2);
+    const double g2 = fe_map_fast<3>(z2 * zi, kG2a, kG2b, P.K + 7, P.C2[2], xi2);
+    const double gi = rcp(g0 + g1 + g2);
+    return (g0 * c0 + g1 * c1 + g2 * c2) * gi;
+  }
   double a0, a1, a2;
   if (!FE && P.weights == WJS) {
     const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
