@@ -76,10 +76,16 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     }
     double zb0, zb1, zb2;
     if (map) {
-      double d0, d1, d2;
-      const double g0 = fe_g_d<SPEC>(0, z0, P, &d0);
-      const double g1 = fe_g_d<SPEC>(1, z1, P, &d1);
-      const double g2 = fe_g_d<SPEC>(2, z2, P, &d2);
+      double d0, d1, d2, g0, g1, g2;
+      if constexpr (FE) {
+        g0 = fe_map_fast_d<3>(z0, kG0a, kG0b, P.K, P.C2[0], P.xi, &d0);
+        g1 = fe_map_fast_d<4>(z1, kG1a, kG1b, P.K + 3, P.C2[1], P.xi, &d1);
+        g2 = fe_map_fast_d<3>(z2, kG2a, kG2b, P.K + 7, P.C2[2], P.xi, &d2);
+      } else {
+        g0 = fe_g_d<SPEC>(0, z0, P, &d0);
+        g1 = fe_g_d<SPEC>(1, z1, P, &d1);
+        g2 = fe_g_d<SPEC>(2, z2, P, &d2);
+      }
       const double ginv = rcp(g0 + g1 + g2);
       w0 = g0 * ginv;
       w1 = g1 * ginv;
