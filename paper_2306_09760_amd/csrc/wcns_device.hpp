@@ -178,16 +178,15 @@ __device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double*
 // t_j = tanh(xi (w - nu_j)) = 1 - 2 / D_j, D_j = 1 + q_j, q_j = E K_j:
 //   g(w) = w + sum_j A_j(w) - 2 sum_j A_j(w) / D_j,
 // and the last sum is taken over the common denominator prod_j D_j, so the
-// map costs one reciprocal instead of one per term.  q_j is clamped to
-// [e^-45, e^45]: at either end the term contributes exactly what t_j = -1 or
-// +1 does (A_j / D_j rounds away against the other terms, or D_j rounds to 1),
-// and the products of up to four D_j stay below e^180.
+// map costs one reciprocal instead of one per term.  q_j is clamped above at
+// e^45, where the term contributes exactly what t_j = +1 does (A_j / D_j
+// rounds away against the other terms) and products of up to four D_j stay
+// below e^180; below e^-45, D_j = 1 + q_j rounds to 1 (t_j = -1) by itself.
 template <int NT>
 __device__ __forceinline__ double fe_map_fast(double w, const double (&a)[NT],
                                               const double (&b)[NT], const double* K, double C2,
                                               double xi2) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
-  constexpr double kQlo = 2.8625185805493937e-20;  // e^-45
   constexpr double kQhi = 3.4934271057485095e+19;  // e^45
   double sa = 0.0, sb = 1.0;
   for (int j = 0; j < NT; ++j) {
@@ -198,8 +197,7 @@ __device__ __forceinline__ double fe_map_fast(double w, const double (&a)[NT],
   double D[NT], A[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    const double q = __builtin_fmin(__builtin_fmax(E * K[j], kQlo), kQhi);
-    D[j] = q + 1.0;
+    D[j] = __builtin_fmin(E * K[j], kQhi) + 1.0;
     A[j] = __builtin_fma(b[j], w, a[j]);
   }
   double num, den;
@@ -225,14 +223,12 @@ __device__ __forceinline__ double fe_map_fast_d(double w, const double (&a)[NT],
                                                 const double (&b)[NT], const double* K, double C2,
                                                 double xi, double* dg) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
-  constexpr double kQlo = 2.8625185805493937e-20;  // e^-45
   constexpr double kQhi = 3.4934271057485095e+19;  // e^45
   const double E = exp_cw(__builtin_fma(2.0 * xi, w, -C2));
   double D[NT], A[NT], o[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    const double q = __builtin_fmin(__builtin_fmax(E * K[j], kQlo), kQhi);
-    D[j] = q + 1.0;
+    D[j] = __builtin_fmin(E * K[j], kQhi) + 1.0;
     A[j] = __builtin_fma(b[j], w, a[j]);
   }
   // o[j] = prod_{k != j} D_k
@@ -463,6 +459,28 @@ __device__ __forceinline__ double project_field(const RoeState<ND>& r, const dou
 }
 
 // Right eigenvectors applied to characteristic values: U = R W.
+// Row v of the left eigenvector matrix L, for a field that is not a shear
+// field (v = 0, 1 or NV-1): W_v = l . U.  Same quantity as project_field,
+// written as a dot product so that a stencil costs NV operations per node.
+template <int ND, int DIR>
+__device__ __forceinline__ void field_row(const RoeState<ND>& r, int v, double (&l)[ND + 2]) {
+  if (v == 1) {  // entropy: rho - theta
+    l[0] = 1.0 - r.b2;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) l[1 + k] = r.b1 * r.vel[k];
+    l[ND + 1] = -r.b1;
+    return;
+  }
+  // acoustic: (theta +- an) / 2, an = (vel_n rho - m_n) / c
+  const double s = (v == 0) ? 0.5 : -0.5;
+  const double hb1 = 0.5 * r.b1;
+  l[0] = __builtin_fma(s * r.vel[DIR], r.ic, 0.5 * r.b2);
+#pragma unroll
+  for (int k = 0; k < ND; ++k) l[1 + k] = -hb1 * r.vel[k];
+  l[1 + DIR] -= s * r.ic;
+  l[ND + 1] = hb1;
+}
+
 template <int ND, int DIR>
 __device__ __forceinline__ void unproject(const RoeState<ND>& r, const double* W, double* U) {
   const double sum = W[0] + W[1] + W[ND + 1];

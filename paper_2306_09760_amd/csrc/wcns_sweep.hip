@@ -24,6 +24,8 @@
 // before writing that midpoint's flux).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "wcns_internal.hpp"
 #include "wcns_sweep_common.hpp"
 
@@ -150,30 +152,42 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
     double w[5];
     if (proj) {
       if constexpr (NV > 1) {
-        RoeState<ND> rs;
         const double* r = sR + rem;
+        // stencil value s5 sits at LDS node s5 (left) or 5 - s5 (mirrored right)
+        auto gather = [&](auto sidec) {
+          constexpr int SD = decltype(sidec)::value;
+          if (v >= 2 && v < NV - 1) {  // shear field: m_ax - vel_ax rho
+            const int ax = tangential_axis<ND, DIR>(v - 2);
+            const double va = r[ax * TMW];
+            const double* um = u + (1 + ax) * SV;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
-        rs.ic = r[(ND + 2) * TMW];
-        rs.b1 = r[(ND + 4) * TMW];
-        rs.b2 = r[(ND + 5) * TMW];
-        if (side == 0) {
+            for (int s5 = 0; s5 < 5; ++s5) {
+              const int k = (SD ? 5 - s5 : s5) * W;
+              w[s5] = __builtin_fma(-va, u[k], um[k]);
+            }
+          } else {
+            RoeState<ND> rs;
 #pragma unroll
-          for (int s = 0; s < 5; ++s) {
-            double U[NV];
+            for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
+            rs.ic = r[(ND + 2) * TMW];
+            rs.b1 = r[(ND + 4) * TMW];
+            rs.b2 = r[(ND + 5) * TMW];
+            double l[NV];
+            field_row<ND, DIR>(rs, v, l);
 #pragma unroll
-            for (int e = 0; e < NV; ++e) U[e] = u[e * SV + s * W];
-            w[s] = project_field<ND, DIR>(rs, U, v);
+            for (int s5 = 0; s5 < 5; ++s5) {
+              const int k = (SD ? 5 - s5 : s5) * W;
+              double acc = l[0] * u[k];
+#pragma unroll
+              for (int e = 1; e < NV; ++e) acc = __builtin_fma(l[e], u[e * SV + k], acc);
+              w[s5] = acc;
+            }
           }
-        } else {
-#pragma unroll
-          for (int s = 0; s < 5; ++s) {
-            double U[NV];
-#pragma unroll
-            for (int e = 0; e < NV; ++e) U[e] = u[e * SV + (5 - s) * W];
-            w[s] = project_field<ND, DIR>(rs, U, v);
-          }
-        }
+        };
+        if (side)
+          gather(std::integral_constant<int, 1>{});
+        else
+          gather(std::integral_constant<int, 0>{});
       }
     } else {
       const double* uv = u + v * SV;
