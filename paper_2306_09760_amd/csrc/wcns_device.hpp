@@ -98,6 +98,51 @@ __device__ __forceinline__ double exp_cw(double z) {
   return __builtin_ldexp(p, (int)n);
 }
 
+// 2^(k/64), k = 0..63, each correctly rounded (generated in 60-digit decimal
+// arithmetic).  Kernels that call exp_tab copy it into LDS first.
+__device__ constexpr double kExp2Tab64[64] = {
+    0x1.0000000000000p+0, 0x1.02c9a3e778061p+0, 0x1.059b0d3158574p+0, 0x1.0874518759bc8p+0,
+    0x1.0b5586cf9890fp+0, 0x1.0e3ec32d3d1a2p+0, 0x1.11301d0125b51p+0, 0x1.1429aaea92de0p+0,
+    0x1.172b83c7d517bp+0, 0x1.1a35beb6fcb75p+0, 0x1.1d4873168b9aap+0, 0x1.2063b88628cd6p+0,
+    0x1.2387a6e756238p+0, 0x1.26b4565e27cddp+0, 0x1.29e9df51fdee1p+0, 0x1.2d285a6e4030bp+0,
+    0x1.306fe0a31b715p+0, 0x1.33c08b26416ffp+0, 0x1.371a7373aa9cbp+0, 0x1.3a7db34e59ff7p+0,
+    0x1.3dea64c123422p+0, 0x1.4160a21f72e2ap+0, 0x1.44e086061892dp+0, 0x1.486a2b5c13cd0p+0,
+    0x1.4bfdad5362a27p+0, 0x1.4f9b2769d2ca7p+0, 0x1.5342b569d4f82p+0, 0x1.56f4736b527dap+0,
+    0x1.5ab07dd485429p+0, 0x1.5e76f15ad2148p+0, 0x1.6247eb03a5585p+0, 0x1.6623882552225p+0,
+    0x1.6a09e667f3bcdp+0, 0x1.6dfb23c651a2fp+0, 0x1.71f75e8ec5f74p+0, 0x1.75feb564267c9p+0,
+    0x1.7a11473eb0187p+0, 0x1.7e2f336cf4e62p+0, 0x1.82589994cce13p+0, 0x1.868d99b4492edp+0,
+    0x1.8ace5422aa0dbp+0, 0x1.8f1ae99157736p+0, 0x1.93737b0cdc5e5p+0, 0x1.97d829fde4e50p+0,
+    0x1.9c49182a3f090p+0, 0x1.a0c667b5de565p+0, 0x1.a5503b23e255dp+0, 0x1.a9e6b5579fdbfp+0,
+    0x1.ae89f995ad3adp+0, 0x1.b33a2b84f15fbp+0, 0x1.b7f76f2fb5e47p+0, 0x1.bcc1e904bc1d2p+0,
+    0x1.c199bdd85529cp+0, 0x1.c67f12e57d14bp+0, 0x1.cb720dcef9069p+0, 0x1.d072d4a07897cp+0,
+    0x1.d5818dcfba487p+0, 0x1.da9e603db3285p+0, 0x1.dfc97337b9b5fp+0, 0x1.e502ee78b3ff6p+0,
+    0x1.ea4afa2a490dap+0, 0x1.efa1bee615a27p+0, 0x1.f50765b6e4540p+0, 0x1.fa7c1819e90d8p+0,
+};
+
+// e^z for |z| <= 708 through the table above (Tang's method, ACM TOMS 15
+// (1989)): z = (64 m + k) ln2/64 + r with |r| <= ln2/128, reduced with a
+// 36-bit head of ln2/64 (exact for |64 m + k| < 2^17) and its tail; e^r - 1
+// from the degree-6 Taylor polynomial (truncation below 3e-20); the result
+// is 2^m (T_k + T_k (e^r - 1)).  T points to the table in LDS.
+__device__ __forceinline__ double exp_tab(double z, const double* T) {
+  constexpr double kInv = 0x1.71547652b82fep+6;       // 64 / ln 2
+  constexpr double kHi = 0x1.62e42fefa0000p-7;        // ln2/64, 36 significant bits
+  constexpr double kLo = 0x1.cf79abc9e3b3ap-46;       // ln2/64 - kHi
+  const double n = __builtin_rint(z * kInv);
+  double r = __builtin_fma(-n, kHi, z);
+  r = __builtin_fma(-n, kLo, r);
+  const int ni = (int)n;
+  const double t = T[ni & 63];
+  double p = 1.0 / 720.0;
+  p = __builtin_fma(p, r, 1.0 / 120.0);
+  p = __builtin_fma(p, r, 1.0 / 24.0);
+  p = __builtin_fma(p, r, 1.0 / 6.0);
+  p = __builtin_fma(p, r, 0.5);
+  p = __builtin_fma(p, r, 1.0);
+  p *= r;
+  return __builtin_ldexp(__builtin_fma(t, p, t), ni >> 6);
+}
+
 // tanh(x) = sign(x) (1 - e^{-2|x|}) / (1 + e^{-2|x|}); +-1 for |x| >= 20.
 __device__ __forceinline__ double tanh_sat(double x) {
   const double ax = __builtin_fabs(x);
@@ -182,10 +227,10 @@ __device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double*
 // e^45, where the term contributes exactly what t_j = +1 does (A_j / D_j
 // rounds away against the other terms) and products of up to four D_j stay
 // below e^180; below e^-45, D_j = 1 + q_j rounds to 1 (t_j = -1) by itself.
-template <int NT>
+template <int NT, bool TAB>
 __device__ __forceinline__ double fe_map_fast(double w, const double (&a)[NT],
                                               const double (&b)[NT], const double* K, double C2,
-                                              double xi2) {
+                                              double xi2, const double* xt) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
   constexpr double kQhi = 3.4934271057485095e+19;  // e^45
   double sa = 0.0, sb = 1.0;
@@ -193,7 +238,8 @@ __device__ __forceinline__ double fe_map_fast(double w, const double (&a)[NT],
     sa += a[j];
     sb += b[j];
   }
-  const double E = exp_cw(__builtin_fma(xi2, w, -C2));
+  const double z = __builtin_fma(xi2, w, -C2);
+  const double E = TAB ? exp_tab(z, xt) : exp_cw(z);
   double D[NT], A[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
@@ -263,9 +309,10 @@ __device__ __forceinline__ double fe_map_fast_d(double w, const double (&a)[NT],
 
 // Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
 // u_{i+2}) = (a, b, c, e, f).
-template <int SPEC = SPEC_GENERIC>
+// xt: the kExp2Tab64 table in LDS (TAB = true), else unused.
+template <int SPEC = SPEC_GENERIC, bool TAB = false>
 __device__ __forceinline__ double interp5(const InterpParams& P, double a, double b, double c,
-                                          double e, double f) {
+                                          double e, double f, const double* xt = nullptr) {
   constexpr bool FE = (SPEC == SPEC_FE);
   // Candidates, eq. 5.
   const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
@@ -301,9 +348,9 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
     const double z2 = D2 * (q2 + t2) * (q0 * q1);
     const double zi = rcp(z0 + z1 + z2);
     const double xi2 = 2.0 * P.xi;
-    const double g0 = fe_map_fast<3>(z0 * zi, kG0a, kG0b, P.K, P.C2[0], xi2);
-    const double g1 = fe_map_fast<4>(z1 * zi, kG1a, kG1b, P.K + 3, P.C2[1], xi2);
-    const double g2 = fe_map_fast<3>(z2 * zi, kG2a, kG2b, P.K + 7, P.C2[2], xi2);
+    const double g0 = fe_map_fast<3, TAB>(z0 * zi, kG0a, kG0b, P.K, P.C2[0], xi2, xt);
+    const double g1 = fe_map_fast<4, TAB>(z1 * zi, kG1a, kG1b, P.K + 3, P.C2[1], xi2, xt);
+    const double g2 = fe_map_fast<3, TAB>(z2 * zi, kG2a, kG2b, P.K + 7, P.C2[2], xi2, xt);
     const double gi = rcp(g0 + g1 + g2);
     return (g0 * c0 + g1 * c1 + g2 * c2) * gi;
   }

@@ -40,7 +40,7 @@ struct SweepLayout {
   static constexpr int SV = TN * W;                    // LDS stride between variables
   static constexpr int LW = W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4;
   static constexpr int LTMW = TMW == 128 ? 7 : 8;
-  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(NR + 2 * NV) * TMW;
+  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(NR + 2 * NV) * TMW + 64;
   static_assert(TMW == 128 || TMW == 256, "tile must hold 128 or 256 midpoints");
   static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
@@ -56,6 +56,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
   double* sU = smem;
   double* sR = sU + NV * SV;
   double* sW = sR + NR * TMW;
+  double* sX = sW + 2 * NV * TMW;  // kExp2Tab64
   const int tid = threadIdx.x;
   const int G = a.diff ? 5 : 4;
   const int TL = TM - (a.diff ? 5 : 3);
@@ -104,6 +105,9 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
   const int64_t nb = i0 - G;
 
   // load
+  if constexpr (SPEC == SPEC_FE) {
+    if (tid < 64) sX[tid] = kExp2Tab64[tid];
+  }
   for (int idx = tid; idx < SV; idx += NT) {
     const int k = idx >> LW, c = idx & (W - 1);
     const int cc = c < ncol ? c : ncol - 1;
@@ -199,7 +203,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
         for (int s = 0; s < 5; ++s) w[s] = uv[(5 - s) * W];
       }
     }
-    sW[q] = interp5<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4]);  // q = slot TMW + rem
+    sW[q] = interp5<SPEC, SPEC == SPEC_FE>(a.ip, w[0], w[1], w[2], w[3], w[4], sX);
   }
   __syncthreads();
 
@@ -291,7 +295,8 @@ bool sweep_shape_ok(int nv, int dir, int tm, int w) {
   const bool known = (tm == 16 && w == 8) || (tm == 32 && w == 4) || (tm == 32 && w == 8) ||
                      (tm == 64 && w == 4);
   if (!known) return false;
-  const size_t lds = sizeof(double) * ((size_t)nv * (tm + 5) * w + (size_t)(3 * nv + 4) * tm * w);
+  const size_t nr = nv > 1 ? nv + 4 : 0;
+  const size_t lds = sizeof(double) * ((size_t)nv * (tm + 5) * w + (nr + 2 * nv) * (size_t)tm * w + 64);
   return lds <= 64 * 1024;
 }
 
