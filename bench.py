@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch the step eagerly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the xi = 1e6 and plain-form (1D per problem, 2D, 3D) timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -59,11 +61,12 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary
-    (rocprofv3 FETCH_SIZE and WRITE_SIZE passes, scaled by a plain copy of
-    known size), or None if it was taken on other sources."""
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+def measured_counters(kernel):
+    """Counter figures of ``kernel`` from the committed summary (rocprofv3
+    FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy of known size, and
+    the SQ instruction counters), or None if they were taken on other
+    sources."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_counters.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -71,16 +74,68 @@ def measured_traffic(kernel):
         return None
     if rec.get("source_digest") != source_digest() or rec.get("kernel") != kernel:
         return None
-    return rec.get("bytes_per_launch")
+    return rec
 
 
-def algorithmic_flops_per_point_stage(ora, prob_kw, U_small, n_small):
-    """Arithmetic of one residual per node from the oracle's operation tally
-    (each +, -, x, /, sqrt and tanh counts as one flop), plus the stage
-    combine (5 per variable)."""
-    P = ora.Problem(**prob_kw, n=(n_small,), h=(1.0 / (n_small - 1),))
-    c = P.count_residual_ops(U_small)
-    return sum(c.values()) / n_small + 5 * 3, c
+# Algorithmic flops per grid-point RK3 stage of the 1D Euler batch, by weight
+# choice: the oracle's operation tally of one residual per node (each +, -,
+# x, /, sqrt and tanh counts once; characteristic projection, MND6, LLF) on a
+# 512-node shock tube, plus the stage combine (5 per variable).  A CPU test
+# recomputes each entry with the oracle.
+FLOPS_PER_POINT_STAGE = {
+    "fe": 1286.208984375,
+    "js": 706.833984375,
+    "z": 767.185546875,
+    "pfe": 771.216796875,
+    "linear": 616.306640625,
+}
+
+
+_CPU_JOB = {}   # the batch, set before the worker processes fork
+
+
+def _oracle_steps(probs):
+    """One SSP-RK3 step (CFL 0.5) of each listed problem with the oracle."""
+    import oracle
+    U_host, meta, okw = _CPU_JOB["U"], _CPU_JOB["meta"], _CPU_JOB["okw"]
+    o = meta["offsets"]
+    npts = 0
+    for p in probs:
+        n = int(o[p + 1] - o[p])
+        P = oracle.Problem(system="euler", ndim=1, n=(n,), h=(meta["h"][p],), **okw)
+        Up = U_host[:, o[p]:o[p + 1]]
+        P.rk3_step(Up, P.cfl_dt(Up, 0.5))
+        npts += n
+    return npts
+
+
+def cpu_baseline(seed, okw):
+    """The oracle on the host: one step of every ninth problem on one thread,
+    then one step of every problem over all cores (forked worker processes,
+    started before this process touches the GPU)."""
+    import multiprocessing as mp
+
+    from paper_2306_09760_amd import workloads as W
+    _, U_host, meta = W.shock_tube_batch(seed=seed)
+    nprob = len(meta["lengths"])
+    _CPU_JOB.update(U=U_host, meta=meta, okw=okw)
+    t0 = time.perf_counter()
+    n1 = _oracle_steps(list(range(0, nprob, 9)))
+    t1 = time.perf_counter() - t0
+    cores = max(1, min(16, os.cpu_count() or 1))
+    jobs = [list(range(k, nprob, cores)) for k in range(cores)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(abs, range(cores))  # workers up before the clock starts
+        t0 = time.perf_counter()
+        nall = sum(pool.map(_oracle_steps, jobs))
+        tall = time.perf_counter() - t0
+    return {"value": 3 * nall / tall, "unit": "grid-point RK3-stage updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"one SSP-RK3 step of all {nprob} problems of the batch ({nall} points) in "
+                      f"{cores} worker processes, {tall:.1f} s wall",
+            "single_thread_value": 3 * n1 / t1,
+            "single_thread_sample": f"one step of every ninth problem ({n1} points, {t1:.1f} s)"}
 
 
 def main():
@@ -91,13 +146,17 @@ def main():
               "library (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    proto = dict(weights=args.weights, xi=args.xi, kappa=0.5, zpow=2, eps=1e-40, diff="mnd6",
+                 charproj=True, gamma=1.4, bc="transmissive")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.seed, proto)
+
     import torch
     from paper_2306_09760_amd import workloads as W
     from paper_2306_09760_amd.solver import BatchPlan, Plan
 
     dev = torch.device("cuda")
-    proto = dict(weights=args.weights, xi=args.xi, kappa=0.5, zpow=2, eps=1e-40, diff="mnd6",
-                 charproj=True, gamma=1.4, bc="transmissive")
     prob, U_host, meta = W.shock_tube_batch(seed=args.seed)
     lengths = meta["lengths"].astype(np.int64)
     B = BatchPlan(meta["offsets"], meta["h"], **proto)
@@ -164,11 +223,7 @@ def main():
     kernel = "sweep_kernel<3, 0, true, 1, %d, 1>" % tile
     total_pts = int(lengths.sum())
 
-    import oracle
-    small = W.shock_tube(1.0, 0.75, 1.0, 0.125, 0.0, 0.1, 512)
-    okw = {k: v for k, v in proto.items()}
-    flops_pt, counts = algorithmic_flops_per_point_stage(
-        oracle, dict(system="euler", ndim=1, **okw), small[1], 512)
+    flops_pt = FLOPS_PER_POINT_STAGE[args.weights]
     kernel_flops = flops_pt * total_pts
     achieved_tflops = kernel_flops / (kernel_ms * 1e-3) / 1e12
     bytes_pt = 3 * 3 * 8  # stage 2/3 reads U^(k) and U^n, writes U^(k+1)
@@ -242,26 +297,67 @@ def main():
                    "ratio_rollout_with_recompute": round(b_rev / f_rev, 3),
                    "note": "adjoint step recomputes its two stage states"}
 
-    # ---- CPU oracle on a bounded sample ----------------------------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        sample = np.arange(0, B.nprob, 3)
-        o = meta["offsets"]
-        t0 = time.perf_counter()
-        npts = 0
-        for p in sample:
-            P = oracle.Problem(system="euler", ndim=1, n=(int(lengths[p]),), h=(meta["h"][p],),
-                               **okw)
-            Up = U_host[:, o[p]:o[p + 1]]
-            dtp = P.cfl_dt(Up, 0.5)
-            P.rk3_step(Up, dtp)
-            npts += int(lengths[p])
-        cpu_s = time.perf_counter() - t0
-        cpu = {"value": 3 * npts / cpu_s, "unit": "grid-point RK3-stage updates/s", "cores": 1,
-               "kind": "oracle",
-               "sample": "one SSP-RK3 step of every third problem of the batch "
-                         f"({len(sample)} problems, {npts} points, {cpu_s:.1f} s, single thread)"}
+    # ---- other forms on the same GPU --------------------------------------
+    forms = None
+    if not args.no_forms:
+        def time_launches(fn, n):
+            fn()
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record()
+            for _ in range(n):
+                fn()
+            f1.record()
+            torch.cuda.synchronize()
+            return f0.elapsed_time(f1) / n
 
+        forms = {"batch_stage_xi_%g" % args.xi: {
+            "kernel_ms": round(kernel_ms, 4), "pt_stage_per_s": total_pts / (kernel_ms * 1e-3)}}
+        # the batch at xi = 1e6: per-term exponentials (generic instantiation)
+        B6 = BatchPlan(meta["offsets"], meta["h"], **dict(proto, xi=1e6))
+        B6.autotune(U0)
+        t6 = torch.zeros(B6.nprob, dtype=torch.float64, device=dev)
+        B6.cfl(U0, t6, T_END, 0.5)
+        ms6 = time_launches(lambda: B6.stage(2, U1, U0, out), 10)
+        forms["batch_stage_xi_1e6"] = {"kernel_ms": round(ms6, 4),
+                                       "pt_stage_per_s": total_pts / (ms6 * 1e-3)}
+        del B6
+        # plain form on the batch workload: the first 256 tubes, one plan each
+        o = meta["offsets"]
+        plains = []
+        for p in range(256):
+            n = int(lengths[p])
+            Pp = Plan(system="euler", ndim=1, n=(n,), h=(float(meta["h"][p]),),
+                      **{k: v for k, v in proto.items()})
+            plains.append((Pp, U0[:, o[p]:o[p + 1]].clone()))
+        npl = int(lengths[:256].sum())
+
+        def plain_steps():
+            for Pp, Up in plains:
+                Pp.rk3_step(Up)
+        msp = time_launches(plain_steps, 3)
+        forms["plain_1d_one_plan_per_tube"] = {
+            "workload": "first 256 tubes of the batch (%d points), one plan and one CFL step each" % npl,
+            "ms_per_step": round(msp, 4), "pt_stage_per_s": 3 * npl / (msp * 1e-3)}
+        del plains
+        # plain form on structured grids
+        for name, (pk, Uh, _) in (
+                ("plain_2d_riemann_2048", W.riemann2d(seed=args.seed, n=2048)),
+                ("plain_3d_turbulence_256", W.turbulence3d(seed=args.seed, n=256))):
+            Pg = Plan(**pk, weights=args.weights, xi=args.xi)
+            Ug = torch.from_numpy(Uh).to(dev)
+            tiles = Pg.autotune(Ug)
+            msg = time_launches(lambda: Pg.rk3_step(Ug), 3)
+            npg = int(np.prod(Uh.shape[1:]))
+            forms[name] = {"ms_per_step": round(msg, 4), "pt_stage_per_s": 3 * npg / (msg * 1e-3),
+                           "tiles": list(tiles)}
+            del Pg, Ug
+        if adjoint is not None:
+            n5 = 1024 * 1024
+            forms["adjoint_2d_1024"] = {
+                "forward_pt_stage_per_s": 3 * n5 / (adjoint["forward_step_ms"] * 1e-3),
+                "adjoint_pt_stage_per_s": 3 * n5 / (adjoint["adjoint_step_ms"] * 1e-3)}
+
+    cnt = measured_counters(kernel)
     line = {
         "metric": "grid-point RK3-stage updates/s (FP64), % HBM roofline; adjoint/forward time ratio",
         "value": value,
@@ -288,15 +384,21 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP64_TFLOPS,
-            "traffic": measured_traffic(kernel),
+            "traffic": cnt["bytes_per_launch"] if cnt else None,
             "kernel": kernel,
             "kernel_ms": kernel_ms,
             "flops_per_point_stage": flops_pt,
             "hbm_algorithmic_gbs": hbm_gbs,
             "hbm_frac": hbm_gbs / PEAK_HBM_GBS,
+            "hbm_measured_gbs": (cnt["bytes_per_launch"] / (kernel_ms * 1e-3) / 1e9) if cnt else None,
+            # wave instructions issued / (256 CU x 4 SIMD x 2.4 GHz / 4 cycles each)
+            "valu_issue_frac": (cnt["valu_wave_insts"] * 4 / (1024 * 2.4e9 * kernel_ms * 1e-3))
+                               if cnt else None,
+            "fp64_share_of_valu": (cnt["fp64_wave_insts"] / cnt["valu_wave_insts"]) if cnt else None,
         },
         "cpu_baseline": cpu,
         "adjoint_forward": adjoint,
+        "forms": forms,
         "status_word": bad,
         "wall_s": wall,
     }
