@@ -20,8 +20,10 @@
 //   gather   per node: the six midpoint contributions, ghost positions folded
 //            onto the boundary node (transmissive), the node-flux term of
 //            MND6, and Ubar += scale * sum.
-// LDS (doubles): sU[NV][TM+5][W] | sR[NR][TMW] | sRB[NR][TMW] | sW[2NV][TMW]
-// | sWB[6 NV][TMW], TMW = TM W.
+// LDS (doubles): sU[NV][TM+5][W] | sR[NR][TMW] | sWB[6 NV][TMW] (its first
+// 2 NV rows hold the interpolated values and their cotangents first) | the
+// 64-entry exp table, TMW = TM W.  The Roe-quantity cotangent of a midpoint
+// stays in its lane's registers from the flux VJP to the projection VJP.
 #include <hip/hip_runtime.h>
 
 #include "wcns_adjoint_device.hpp"
@@ -39,7 +41,7 @@ struct AdjLayout {
   static constexpr int SV = TN * W;
   static constexpr int LW = W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4;
   static constexpr int LTMW = TMW == 64 ? 6 : TMW == 128 ? 7 : 8;
-  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(2 * NR + 8 * NV) * TMW;
+  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(NR + 6 * NV) * TMW + 64;
   static_assert(TMW == 64 || TMW == 128 || TMW == 256, "tile must hold 64, 128 or 256 midpoints");
   static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
@@ -52,19 +54,32 @@ __device__ __forceinline__ double rbar_at(const double* Rb, int64_t base, int64_
   return Rb[base + j * stride];
 }
 
+#ifndef WCNS_ADJ_WAVES_PER_SIMD
+#define WCNS_ADJ_WAVES_PER_SIMD 4
+#endif
+// Register budget for WCNS_ADJ_WAVES_PER_SIMD waves per SIMD (the LDS of a
+// 128-midpoint tile allows four workgroups per CU).
 template <int NV, int DIR, int SPEC, int TM, int W>
-__global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(WCNS_ADJ_WAVES_PER_SIMD)))
+    adj_sweep_kernel(AdjArgs a, TileGeom g) {
   using L = AdjLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TMW = L::TMW, SV = L::SV;
   constexpr int LW = L::LW, LTMW = L::LTMW;
   constexpr int NT = 256;
   constexpr int TL = TM - 5;
   extern __shared__ double smem[];
+  static_assert(TMW <= NT, "one midpoint per lane in the per-midpoint phases");
   double* sU = smem;
   double* sR = sU + NV * SV;
-  double* sRB = sR + NR * TMW;
-  double* sW = sRB + NR * TMW;
-  double* sWB = sW + 2 * NV * TMW;
+  double* sWB = sR + NR * TMW;
+  // Interpolated values and their cotangents (left field v in row v, right in
+  // row NV + v) share rows 0 .. 2NV-1 of sWB: the interpolation VJP task of
+  // (field v, midpoint) reads exactly its own two entries before writing
+  // stencil slots 0 and 1 of field v over them.
+  double* sW = sWB;
+  double* sX = sWB + 6 * NV * TMW;  // kExp2Tab64
+  constexpr bool TAB = SPEC == SPEC_FE;
   const int tid = threadIdx.x;
 
   const int64_t tile = blockIdx.x;
@@ -96,6 +111,9 @@ __global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
   const int64_t nb = i0 - 5;  // position of LDS node 0
 
   // load
+  if constexpr (TAB) {
+    if (tid < 64) sX[tid] = kExp2Tab64[tid];
+  }
   for (int idx = tid; idx < SV; idx += NT) {
     const int k = idx >> LW, c = idx & (W - 1);
     const int cc = c < ncol ? c : ncol - 1;
@@ -150,13 +168,28 @@ __global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
     const double* u = sU + rem;
     if (proj) {
       if constexpr (NV > 1) {
-        const RoeState<ND> rs = load_roe(rem);
+        const double* rr = sR + rem;
+        if (v >= 2 && v < NV - 1) {  // shear field: m_ax - vel_ax rho
+          const int ax = tangential_axis<ND, DIR>(v - 2);
+          const double va = rr[ax * TMW];
 #pragma unroll
-        for (int s = 0; s < 6; ++s) {
-          double U[NV];
+          for (int s = 0; s < 6; ++s) w[s] = __builtin_fma(-va, u[s * W], u[(1 + ax) * SV + s * W]);
+        } else {
+          RoeState<ND> rs;
 #pragma unroll
-          for (int e = 0; e < NV; ++e) U[e] = u[e * SV + s * W];
-          w[s] = project_field<ND, DIR>(rs, U, v);
+          for (int k = 0; k < ND; ++k) rs.vel[k] = rr[k * TMW];
+          rs.ic = rr[(ND + 2) * TMW];
+          rs.b1 = rr[(ND + 4) * TMW];
+          rs.b2 = rr[(ND + 5) * TMW];
+          double l[NV];
+          field_row<ND, DIR>(rs, v, l);
+#pragma unroll
+          for (int s = 0; s < 6; ++s) {
+            double acc = l[0] * u[s * W];
+#pragma unroll
+            for (int e = 1; e < NV; ++e) acc = __builtin_fma(l[e], u[e * SV + s * W], acc);
+            w[s] = acc;
+          }
         }
       }
     } else {
@@ -174,14 +207,20 @@ __global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
     const int v = side ? slot - NV : slot;
     double w[6];
     stencil(rem, v, w);
-    sW[q] = side ? interp5<SPEC>(a.ip, w[5], w[4], w[3], w[2], w[1])
-                 : interp5<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4]);
+    sW[q] = side ? interp5<SPEC, TAB>(a.ip, w[5], w[4], w[3], w[2], w[1], sX)
+                 : interp5<SPEC, TAB>(a.ip, w[0], w[1], w[2], w[3], w[4], sX);
   }
   __syncthreads();
 
-  // flux VJP per midpoint: sW <- cotangents of the interpolated values
-#pragma unroll 1
-  for (int q = tid; q < TMW; q += NT) {
+  // flux VJP per midpoint: sW <- cotangents of the interpolated values; the
+  // cotangent of the Roe quantities stays in this lane's registers until the
+  // projection VJP below
+  RoeBar<ND> rb;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) rb.vel[k] = 0.0;
+  rb.H = rb.c = rb.ic = rb.q2h = rb.b1 = rb.b2 = 0.0;
+  if (tid < TMW) {
+    const int q = tid;
     const int t = q >> LW, c = q & (W - 1);
     const int cc = c < ncol ? c : ncol - 1;
     const int64_t m = i0 - 3 + t;
@@ -219,10 +258,6 @@ __global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
         unproject<ND, DIR>(rs, WL, UL);
         unproject<ND, DIR>(rs, WR, UR);
         llf_vjp<ND, DIR>(UL, UR, a.pp.gamma, Fb, ULb, URb);
-        RoeBar<ND> rb;
-#pragma unroll
-        for (int k = 0; k < ND; ++k) rb.vel[k] = 0.0;
-        rb.H = rb.c = rb.ic = rb.q2h = rb.b1 = rb.b2 = 0.0;
         double WLb[NV], WRb[NV];
         unproject_vjp<ND, DIR>(rs, WL, ULb, WLb, rb);
         unproject_vjp<ND, DIR>(rs, WR, URb, WRb, rb);
@@ -231,15 +266,6 @@ __global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
           sW[v * TMW + q] = WLb[v];
           sW[(NV + v) * TMW + q] = WRb[v];
         }
-        double* rr = sRB + q;
-#pragma unroll
-        for (int k = 0; k < ND; ++k) rr[k * TMW] = rb.vel[k];
-        rr[(ND + 0) * TMW] = rb.H;
-        rr[(ND + 1) * TMW] = rb.c;
-        rr[(ND + 2) * TMW] = rb.ic;
-        rr[(ND + 3) * TMW] = rb.q2h;
-        rr[(ND + 4) * TMW] = rb.b1;
-        rr[(ND + 5) * TMW] = rb.b2;
       } else {
         llf_vjp<ND, DIR>(WL, WR, a.pp.gamma, Fb, ULb, URb);
 #pragma unroll
@@ -262,10 +288,10 @@ __global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
     stencil(rem, v, w);
 #pragma unroll
     for (int j = 0; j < 6; ++j) wb[j] = 0.0;
-    interp5_vjp<SPEC>(a.ip, w[0], w[1], w[2], w[3], w[4], sW[v * TMW + rem], wb[0], wb[1], wb[2],
-                      wb[3], wb[4]);
-    interp5_vjp<SPEC>(a.ip, w[5], w[4], w[3], w[2], w[1], sW[(NV + v) * TMW + rem], wb[5], wb[4],
-                      wb[3], wb[2], wb[1]);
+    interp5_vjp<SPEC, TAB>(a.ip, w[0], w[1], w[2], w[3], w[4], sW[v * TMW + rem], wb[0], wb[1],
+                           wb[2], wb[3], wb[4], sX);
+    interp5_vjp<SPEC, TAB>(a.ip, w[5], w[4], w[3], w[2], w[1], sW[(NV + v) * TMW + rem], wb[5],
+                           wb[4], wb[3], wb[2], wb[1], sX);
 #pragma unroll
     for (int j = 0; j < 6; ++j) sWB[(j * NV + v) * TMW + rem] = wb[j];
   }
@@ -274,19 +300,9 @@ __global__ void __launch_bounds__(256) adj_sweep_kernel(AdjArgs a, TileGeom g) {
   // projection and Roe-average VJP per midpoint (in place: slot j's NV rows)
   if constexpr (NV > 1) {
     if (proj) {
-#pragma unroll 1
-      for (int q = tid; q < TMW; q += NT) {
+      if (tid < TMW) {
+        const int q = tid;
         const RoeState<ND> rs = load_roe(q);
-        RoeBar<ND> rb;
-        const double* rr = sRB + q;
-#pragma unroll
-        for (int k = 0; k < ND; ++k) rb.vel[k] = rr[k * TMW];
-        rb.H = rr[(ND + 0) * TMW];
-        rb.c = rr[(ND + 1) * TMW];
-        rb.ic = rr[(ND + 2) * TMW];
-        rb.q2h = rr[(ND + 3) * TMW];
-        rb.b1 = rr[(ND + 4) * TMW];
-        rb.b2 = rr[(ND + 5) * TMW];
         const double* u = sU + q;
 #pragma unroll
         for (int j = 0; j < 6; ++j) {

@@ -21,10 +21,12 @@ __device__ __forceinline__ double fe_g_d(int i, double w, const InterpParams& P,
 
 // Cotangent of interp5's inputs (a, b, c, e, f) for output cotangent yb;
 // accumulates into the five references.
-template <int SPEC = SPEC_GENERIC>
+// xt: the kExp2Tab64 table in LDS (TAB = true, FE specialisation only).
+template <int SPEC = SPEC_GENERIC, bool TAB = false>
 __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, double b, double c,
                                             double e, double f, double yb, double& ab, double& bb,
-                                            double& cb, double& eb, double& fb) {
+                                            double& cb, double& eb, double& fb,
+                                            const double* xt = nullptr) {
   constexpr bool FE = (SPEC == SPEC_FE);
   const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
   const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
@@ -78,9 +80,9 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     if (map) {
       double d0, d1, d2, g0, g1, g2;
       if constexpr (FE) {
-        g0 = fe_map_fast_d<3>(z0, kG0a, kG0b, P.K, P.C2[0], P.xi, &d0);
-        g1 = fe_map_fast_d<4>(z1, kG1a, kG1b, P.K + 3, P.C2[1], P.xi, &d1);
-        g2 = fe_map_fast_d<3>(z2, kG2a, kG2b, P.K + 7, P.C2[2], P.xi, &d2);
+        g0 = fe_map_fast_d<3, TAB>(z0, kG0a, kG0b, P.K, P.C2[0], P.xi, &d0, xt);
+        g1 = fe_map_fast_d<4, TAB>(z1, kG1a, kG1b, P.K + 3, P.C2[1], P.xi, &d1, xt);
+        g2 = fe_map_fast_d<3, TAB>(z2, kG2a, kG2b, P.K + 7, P.C2[2], P.xi, &d2, xt);
       } else {
         g0 = fe_g_d<SPEC>(0, z0, P, &d0);
         g1 = fe_g_d<SPEC>(1, z1, P, &d1);

@@ -264,13 +264,14 @@ __device__ __forceinline__ double fe_map_fast(double w, const double (&a)[NT],
 // fe_map_fast together with g'(w) = 1 + sum_j [b_j t_j + xi A_j (1 - t_j^2)],
 // where t_j = 1 - 2 / D_j and 1 - t_j^2 = 4 (1 / D_j)(1 - 1 / D_j); the
 // 1 / D_j come from the one reciprocal of prod_j D_j.
-template <int NT>
+template <int NT, bool TAB = false>
 __device__ __forceinline__ double fe_map_fast_d(double w, const double (&a)[NT],
                                                 const double (&b)[NT], const double* K, double C2,
-                                                double xi, double* dg) {
+                                                double xi, double* dg, const double* xt = nullptr) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
   constexpr double kQhi = 3.4934271057485095e+19;  // e^45
-  const double E = exp_cw(__builtin_fma(2.0 * xi, w, -C2));
+  const double z = __builtin_fma(2.0 * xi, w, -C2);
+  const double E = TAB ? exp_tab(z, xt) : exp_cw(z);
   double D[NT], A[NT], o[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
