@@ -436,6 +436,18 @@ struct RoeState {
   double H, c, ic, q2h, b1, b2;   // q2h = |u|^2 / 2
 };
 
+// Fills q2h, b1 and b2 of a Roe state from vel and ic, by the same operations
+// as roe_average (so tiles may keep only vel, H, c and ic).
+template <int ND>
+__device__ __forceinline__ void roe_derived(RoeState<ND>& r, double gamma) {
+  double q2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < ND; ++k) q2 += r.vel[k] * r.vel[k];
+  r.q2h = 0.5 * q2;
+  r.b1 = (gamma - 1.0) * r.ic * r.ic;
+  r.b2 = r.q2h * r.b1;
+}
+
 template <int ND>
 __device__ __forceinline__ RoeState<ND> roe_average(const double* UA, const double* UB,
                                                     double gamma) {

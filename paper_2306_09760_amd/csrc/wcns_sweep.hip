@@ -34,7 +34,7 @@ namespace wcns {
 template <int NV, int TM, int W>
 struct SweepLayout {
   static constexpr int ND = NV > 1 ? NV - 2 : 1;
-  static constexpr int NR = NV > 1 ? NV - 2 + 6 : 0;  // vel[ND], H, c, ic, q2h, b1, b2
+  static constexpr int NR = NV > 1 ? NV - 2 + 3 : 0;  // vel[ND], H, c, ic
   static constexpr int TN = TM + 5;                    // nodes per column
   static constexpr int TMW = TM * W;                   // midpoints per tile
   static constexpr int SV = TN * W;                    // LDS stride between variables
@@ -137,9 +137,6 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
         r[(ND + 0) * TMW] = rs.H;
         r[(ND + 1) * TMW] = rs.c;
         r[(ND + 2) * TMW] = rs.ic;
-        r[(ND + 3) * TMW] = rs.q2h;
-        r[(ND + 4) * TMW] = rs.b1;
-        r[(ND + 5) * TMW] = rs.b2;
       }
       __syncthreads();
     }
@@ -174,8 +171,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
 #pragma unroll
             for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
             rs.ic = r[(ND + 2) * TMW];
-            rs.b1 = r[(ND + 4) * TMW];
-            rs.b2 = r[(ND + 5) * TMW];
+            roe_derived<ND>(rs, a.pp.gamma);
             double l[NV];
             field_row<ND, DIR>(rs, v, l);
 #pragma unroll
@@ -228,7 +224,8 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
         for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
         rs.H = r[(ND + 0) * TMW];
         rs.c = r[(ND + 1) * TMW];
-        rs.q2h = r[(ND + 3) * TMW];
+        rs.ic = r[(ND + 2) * TMW];
+        roe_derived<ND>(rs, a.pp.gamma);
         unproject<ND, DIR>(rs, WL, UL);
         unproject<ND, DIR>(rs, WR, UR);
       } else {
@@ -295,7 +292,7 @@ bool sweep_shape_ok(int nv, int dir, int tm, int w) {
   const bool known = (tm == 16 && w == 8) || (tm == 32 && w == 4) || (tm == 32 && w == 8) ||
                      (tm == 64 && w == 4);
   if (!known) return false;
-  const size_t nr = nv > 1 ? nv + 4 : 0;
+  const size_t nr = nv > 1 ? nv + 1 : 0;
   const size_t lds = sizeof(double) * ((size_t)nv * (tm + 5) * w + (nr + 2 * nv) * (size_t)tm * w + 64);
   return lds <= 64 * 1024;
 }
