@@ -130,8 +130,14 @@ def cpu_baseline(seed, okw):
         t0 = time.perf_counter()
         nall = sum(pool.map(_oracle_steps, jobs))
         tall = time.perf_counter() - t0
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": 3 * nall / tall, "unit": "grid-point RK3-stage updates/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": f"one SSP-RK3 step of all {nprob} problems of the batch ({nall} points) in "
                       f"{cores} worker processes, {tall:.1f} s wall",
             "single_thread_value": 3 * n1 / t1,
