@@ -74,6 +74,9 @@ def lib(variant: str = "plain"):
         L.ora_run_steps.argtypes = [D, P, C.c_double, C.c_double, C.c_int64]
         L.ora_run_to_time.argtypes = [D, P, C.c_double, C.c_double, C.c_int64,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.ora_rk4_step.argtypes = [D, P, C.c_double]
+        L.ora_run_to_time_rk.argtypes = [D, P, C.c_double, C.c_double, C.c_int64, C.c_int,
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.ora_interpolate.argtypes = [D, P, P, P]
         L.ora_interpolate.restype = C.c_double
         L.ora_interpolate_jvp.argtypes = [D, P, P, P]
@@ -176,12 +179,25 @@ class Problem:
         bad = lib(self.variant).ora_run_steps(self._ref(), _p(U), cfl, dt, int(nsteps))
         return U, bad
 
-    def run_to_time(self, U, t_end, cfl=0.5, max_steps=10**9):
+    def rk4_step(self, U, dt):
+        """One step of the four-stage scheme of eq. 16."""
+        U = self._u(U).copy()
+        bad = lib(self.variant).ora_rk4_step(self._ref(), _p(U), dt)
+        return U, bad
+
+    def run_to_time(self, U, t_end, cfl=0.5, max_steps=10**9, method="rk3"):
+        """March to t_end (last step clipped) with SSP-RK3 or the RK4 of eq. 16."""
         U = self._u(U).copy()
         s = C.c_int64(0)
         t = C.c_double(0.0)
-        bad = lib(self.variant).ora_run_to_time(self._ref(), _p(U), cfl, t_end, max_steps,
-                                    C.byref(s), C.byref(t))
+        if method == "rk3":
+            bad = lib(self.variant).ora_run_to_time(self._ref(), _p(U), cfl, t_end, max_steps,
+                                                    C.byref(s), C.byref(t))
+        elif method == "rk4":
+            bad = lib(self.variant).ora_run_to_time_rk(self._ref(), _p(U), cfl, t_end, max_steps,
+                                                       4, C.byref(s), C.byref(t))
+        else:
+            raise ValueError(method)
         return U, s.value, t.value, bad
 
     def interpolate(self, u5):

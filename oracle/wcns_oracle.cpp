@@ -567,6 +567,32 @@ int rk3_step(const Desc& D, T* U, double dt) {
   return bad;
 }
 
+// One step of the four-stage Runge-Kutta scheme of eq. 16, in place:
+//   u1 = u + dt/2 L(u),  u2 = u + dt/2 L(u1),  u3 = u + dt L(u2),
+//   u_new = -u/3 + u1/3 + 2 u2/3 + u3/3 + dt/6 L(u3).
+// Returns the state check of the four stage results (0 = all physical).
+template <class T>
+int rk4_step(const Desc& D, T* U, double dt) {
+  const int64_t len = nvars(D) * npoints(D);
+  std::vector<T> U1(len), U2(len), U3(len), L(len);
+  int bad = 0;
+  residual(D, U, L.data());
+  for (int64_t i = 0; i < len; ++i) U1[i] = U[i] + T(0.5 * dt) * L[i];
+  bad |= check_state(D, U1.data());
+  residual(D, U1.data(), L.data());
+  for (int64_t i = 0; i < len; ++i) U2[i] = U[i] + T(0.5 * dt) * L[i];
+  bad |= check_state(D, U2.data());
+  residual(D, U2.data(), L.data());
+  for (int64_t i = 0; i < len; ++i) U3[i] = U[i] + T(dt) * L[i];
+  bad |= check_state(D, U3.data());
+  residual(D, U3.data(), L.data());
+  for (int64_t i = 0; i < len; ++i)
+    U[i] = T(-1.0 / 3.0) * U[i] + T(1.0 / 3.0) * U1[i] + T(2.0 / 3.0) * U2[i] +
+           T(1.0 / 3.0) * U3[i] + T(dt / 6.0) * L[i];
+  bad |= check_state(D, U);
+  return bad;
+}
+
 }  // namespace ora
 
 // ================================================================ C ABI ====
@@ -636,6 +662,27 @@ int ora_run_to_time(const Desc* D, double* U, double cfl, double t_end, int64_t 
     double dt = ora::cfl_dt(*D, U, cfl);
     if (t + dt > t_end) dt = t_end - t;
     bad |= ora::rk3_step(*D, U, dt);
+    t += dt;
+    ++s;
+  }
+  *steps_done = s;
+  *t_done = t;
+  return bad;
+}
+
+int ora_rk4_step(const Desc* D, double* U, double dt) { return ora::rk4_step(*D, U, dt); }
+
+// March to t_end with the CFL step (last step clipped) by SSP-RK3 (method 3)
+// or the four-stage scheme of eq. 16 (method 4).
+int ora_run_to_time_rk(const Desc* D, double* U, double cfl, double t_end, int64_t max_steps,
+                       int method, int64_t* steps_done, double* t_done) {
+  double t = 0.0;
+  int64_t s = 0;
+  int bad = 0;
+  while (t < t_end && s < max_steps) {
+    double dt = ora::cfl_dt(*D, U, cfl);
+    if (t + dt > t_end) dt = t_end - t;
+    bad |= method == 4 ? ora::rk4_step(*D, U, dt) : ora::rk3_step(*D, U, dt);
     t += dt;
     ++s;
   }

@@ -181,6 +181,48 @@ def test_rk3_step_is_the_ssp_rk3_polynomial(ora):
     assert np.allclose(u1, np.real(G * np.exp(1j * 2 * np.pi * 3 * x / (N * h))), atol=1e-13)
 
 
+def test_rk4_step_is_the_fourth_order_taylor_polynomial(ora):
+    """eq. 16 on the linear scheme and one Fourier mode multiplies it by
+    1 + z + z^2/2 + z^3/6 + z^4/24 (the stage coefficients of eq. 16 give
+    classical RK4)."""
+    N, h = 40, 0.05
+    x = h * np.arange(N)
+    theta = 2 * np.pi * 3 / N
+    u0 = np.cos(2 * np.pi * 3 * x / (N * h))
+    P = ora.Problem(system="advection", ndim=1, n=(N,), h=h, weights="linear")
+    dt = 0.02
+    u1, bad = P.rk4_step(u0, dt)
+    assert bad == 0
+    z = -(dt / h) * _symbol(theta)
+    G = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    assert np.allclose(u1, np.real(G * np.exp(1j * 2 * np.pi * 3 * x / (N * h))), atol=1e-13)
+
+
+def test_config1_rk4_matches_discrete_closed_form(ora, W):
+    """The config-1 sine with FE at xi = 1e6 (ideal weights on this data) and
+    400 steps of eq. 16: u_j^n = a Im(G^n e^{i(pi x_j + phi)}) with the RK4
+    amplification factor."""
+    prob, U0, meta = W.advection_sine(seed=0)
+    P = ora.Problem(weights="fe", xi=1e6, **prob)
+    U = U0
+    for _ in range(400):
+        U, bad = P.rk4_step(U, 0.005)
+        assert bad == 0
+    z = -0.5 * _symbol(np.pi * 0.01)
+    G = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    closed = meta["a"] * np.imag(G ** 400 * np.exp(1j * (np.pi * meta["x"] + meta["phi"])))
+    assert np.abs(U[0] - closed).max() < 1e-12
+
+
+def test_rk4_run_to_time_lands_on_t_end(ora, W):
+    prob, U, _ = W.shock_tube(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 101)
+    P = ora.Problem(weights="fe", xi=100.0, **prob)
+    U1, steps, t, bad = P.run_to_time(U, 0.05, cfl=0.3, method="rk4")
+    assert bad == 0 and t == 0.05 and steps > 10
+    # mass is conserved up to the boundary flux of the undisturbed ends
+    assert abs(U1[0].sum() - U[0].sum()) < 1e-12 * U[0].sum()
+
+
 # ------------------------------------------------------------------ invariants --
 @pytest.mark.parametrize("weights", ["js", "z", "fe", "pfe"])
 @pytest.mark.parametrize("ndim", [1, 2, 3])
