@@ -120,6 +120,15 @@ wcns_status wcns_cfl_dt(wcns_plan* plan, const double* U, double cfl, double* dt
 wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev,
                           double cfl, int32_t* status_dev, void* stream);
 
+/* One step in place of the four-stage Runge-Kutta scheme of eq. 16 (the
+   paper's integrator, classical RK4): u1 = u + dt/2 L(u), u2 = u + dt/2
+   L(u1), u3 = u + dt L(u2), u <- -u/3 + u1/3 + 2 u2/3 + u3/3 + dt/6 L(u3).
+   dt_dev, cfl and status_dev as for wcns_rk3_step (the paper runs it at CFL
+   0.3).  Uses `work` (three stage states and one combination buffer).  No
+   host synchronisation: graph-capturable. */
+wcns_status wcns_rk4_step(wcns_plan* plan, double* U, void* work, const double* dt_dev,
+                          double cfl, int32_t* status_dev, void* stream);
+
 /* Ubar += (dL/dU)^T Rbar at state U: the exact vector-Jacobian product of
    the residual, including the weights, the FE mapping, the Roe-averaged
    projection and the flux (conventions at non-smooth points: d|x|/dx = 0

@@ -259,6 +259,37 @@ wcns_status stage(const wcns_plan* P, const double* Uk, const double* U0, double
   return WCNS_OK;
 }
 
+// out = ca*U0 + cb*Uk + cr*dt*L(Uk).
+wcns_status stage_lin(const wcns_plan* P, const double* Uk, const double* U0, double* out,
+                      double ca, double cb, double cr, const double* dt, double* Racc,
+                      int32_t* status, hipStream_t s) {
+  const int nd = P->d.ndim;
+  for (int d = 0; d < nd; ++d) {
+    SweepArgs a;
+    sweep_common(P, d, &a);
+    a.U = Uk;
+    const bool last = (d == nd - 1);
+    int mode;
+    if (last) {
+      mode = MODE_LIN;
+      a.U0 = U0;
+      a.out = out;
+      a.Rin = (nd > 1) ? Racc : nullptr;
+      a.dt = dt;
+      a.status = status;
+      a.ca = ca;
+      a.cb = cb;
+      a.cr = cr;
+    } else {
+      mode = (d == 0) ? MODE_RES : MODE_ACC;
+      a.out = Racc;
+      a.Rin = Racc;
+    }
+    WCNS_HIP(run_sweep(P, d, a, mode, s), "stage sweep launch");
+  }
+  return WCNS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -401,6 +432,38 @@ wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* 
   if ((st = stage(plan, W1, U, W2, 0.75, 0.25, dt, Racc, status_dev, s)) != WCNS_OK) return st;
   if ((st = stage(plan, W2, U, U, 1.0 / 3.0, 2.0 / 3.0, dt, Racc, status_dev, s)) != WCNS_OK) return st;
   return WCNS_OK;
+}
+
+wcns_status wcns_rk4_step(wcns_plan* plan, double* U, void* work, const double* dt_dev, double cfl,
+                          int32_t* status_dev, void* stream) {
+  g_err.clear();
+  if (!plan || !U || !work) return fail(WCNS_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)work;
+  double* U1 = (double*)(w + plan->off_W1);
+  double* U2 = (double*)(w + plan->off_W2);
+  double* U3 = (double*)(w + plan->off_A1);
+  double* A = (double*)(w + plan->off_A2);
+  double* Racc = (double*)(w + plan->off_R);
+  const int64_t len = plan->nv * plan->npts;
+  const double* dt = dt_dev;
+  if (!dt) {
+    if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0 when dt_dev is NULL");
+    double* dtw = (double*)(w + plan->off_dt);
+    WCNS_HIP(launch_cfl(plan->nv, plan->d.ndim, U, plan->npts, plan->d.gamma, plan->ih,
+                        plan->d.adv_speed, cfl, (double*)(w + plan->off_partial), plan->ncfl, dtw, s),
+             "cfl launch");
+    dt = dtw;
+  }
+  wcns_status st;
+  // u1 = u + dt/2 L(u); u2 = u + dt/2 L(u1); u3 = u + dt L(u2)
+  if ((st = stage_lin(plan, U, U, U1, 0.0, 1.0, 0.5, dt, Racc, status_dev, s)) != WCNS_OK) return st;
+  if ((st = stage_lin(plan, U1, U, U2, 1.0, 0.0, 0.5, dt, Racc, status_dev, s)) != WCNS_OK) return st;
+  if ((st = stage_lin(plan, U2, U, U3, 1.0, 0.0, 1.0, dt, Racc, status_dev, s)) != WCNS_OK) return st;
+  // u_new = (-u + u1 + 2 u2)/3 + u3/3 + dt/6 L(u3)
+  WCNS_HIP(launch_lincomb(A, U, -1.0 / 3.0, U1, 1.0 / 3.0, nullptr, 0.0, len, s), "lincomb");
+  WCNS_HIP(launch_axpy_state(A, U2, 2.0 / 3.0, len, s), "axpy");
+  return stage_lin(plan, U3, A, U, 1.0, 1.0 / 3.0, 1.0 / 6.0, dt, Racc, status_dev, s);
 }
 
 wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double* Rbar,

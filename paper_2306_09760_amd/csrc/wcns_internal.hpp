@@ -9,7 +9,9 @@
 
 namespace wcns {
 
-enum SweepMode : int { MODE_RES = 0, MODE_ACC = 1, MODE_STAGE = 2 };
+// MODE_RES: out = R; MODE_ACC: out = Rin + R; MODE_STAGE: out = ca*U0 +
+// cb*(U + dt*R); MODE_LIN: out = ca*U0 + cb*U + cr*dt*R (R includes Rin).
+enum SweepMode : int { MODE_RES = 0, MODE_ACC = 1, MODE_STAGE = 2, MODE_LIN = 3 };
 
 // Which compiled specialisation of the interpolation serves these parameters.
 inline int spec_of(const InterpParams& ip) {
@@ -25,6 +27,7 @@ struct SweepArgs {
   const double* dt;     // device dt (stage mode, non-batch)
   int32_t* status;      // OR-ed bit 0 on a non-physical stage result (may be null)
   double ca, cb;        // stage: out = ca*U0 + cb*(U + dt*R)
+  double cr;            // linear stage: out = ca*U0 + cb*U + cr*dt*R
   int64_t npts;         // stride between variables
   int64_t n[3];         // grid extents (x, y, z)
   int32_t bc;           // boundary type along the sweep direction

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
         base = x0 + other * a.n[0];
       }
     }
-    if (mode == MODE_STAGE) dt = *a.dt;
+    if (mode >= MODE_STAGE) dt = *a.dt;
   }
   const int64_t nb = i0 - G;
 

@@ -25,8 +25,9 @@ __device__ __forceinline__ void flag_status(int32_t* status) {
   if (status) atomicOr(status, 1);
 }
 
-// Writes one node's result according to the sweep mode (MODE_RES, MODE_ACC
-// or MODE_STAGE; `mode` is uniform, so the switch costs a scalar branch).
+// Writes one node's result according to the sweep mode (MODE_RES, MODE_ACC,
+// MODE_STAGE or MODE_LIN; `mode` is uniform, so the switch costs a scalar
+// branch).
 template <int NV>
 __device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gidx, int64_t vstride,
                                         const double (&res)[NV], const double (&Un)[NV],
@@ -44,6 +45,20 @@ __device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t v
   } else if constexpr (MODE == MODE_ACC) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = a.Rin[v * vstride + gidx] + res[v];
+  } else if constexpr (MODE == MODE_LIN) {
+    double y[NV];
+    const double crdt = a.cr * dt;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double r = res[v];
+      if (a.Rin) r += a.Rin[v * vstride + gidx];
+      double s = __builtin_fma(crdt, r, a.cb * Un[v]);
+      if (a.ca != 0.0) s = __builtin_fma(a.ca, a.U0[v * vstride + gidx], s);
+      y[v] = s;
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = y[v];
+    if (!physical<NV>(y, a.pp.gamma)) flag_status(a.status);
   } else {
     double y[NV];
 #pragma unroll
@@ -68,8 +83,10 @@ __device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gi
     emit<NV, MODE_RES>(a, gidx, vstride, res, Un, dt);
   else if (mode == MODE_ACC)
     emit<NV, MODE_ACC>(a, gidx, vstride, res, Un, dt);
-  else
+  else if (mode == MODE_STAGE)
     emit<NV, MODE_STAGE>(a, gidx, vstride, res, Un, dt);
+  else
+    emit<NV, MODE_LIN>(a, gidx, vstride, res, Un, dt);
 }
 
 }  // namespace wcns

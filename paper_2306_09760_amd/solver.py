@@ -88,6 +88,31 @@ class Plan:
                                   _ptr(status), _stream()), "wcns_rk3_step")
         return U
 
+    def rk4_step(self, U, dt=None, cfl=0.3, status=None):
+        """In-place step of the four-stage scheme of eq. 16; dt as rk3_step."""
+        self._check_state(U)
+        check(lib().wcns_rk4_step(self._h, _ptr(U), _ptr(self.work), _ptr(dt), cfl,
+                                  _ptr(status), _stream()), "wcns_rk4_step")
+        return U
+
+    def run_to_time(self, U, t_end, cfl=0.5, method="rk3", max_steps=10 ** 7, status=None):
+        """March U in place to t_end with CFL-limited steps, the last one
+        clipped to land on t_end.  The step size is read back to the host
+        once per step (to clip and count).  Returns (steps, t)."""
+        step = {"rk3": self.rk3_step, "rk4": self.rk4_step}[method]
+        dt = torch.zeros(1, dtype=torch.float64, device=self.device)
+        t, steps = 0.0, 0
+        while t < t_end and steps < max_steps:
+            self.cfl_dt(U, cfl, out=dt)
+            h = float(dt.item())
+            if t + h > t_end:
+                h = t_end - t
+                dt.fill_(h)
+            step(U, dt=dt, status=status)
+            t += h
+            steps += 1
+        return steps, t
+
     def residual_adjoint(self, U, Rbar, Ubar=None):
         """Ubar += (dL/dU)^T Rbar (Ubar zero-initialised if None)."""
         self._check_state(U)

@@ -103,6 +103,45 @@ def shock_tube(rhoL, uL, pL, rhoR, uR, pR, n, length=1.0, x_jump=0.5, gamma=GAMM
     return prob, U, dict(x=x)
 
 
+# ------------------------------------------------- the paper's 1D problems --
+# Sec. 4.2: initial states as printed (eq. 33-36), transmissive ends, end
+# times and point counts of the text (201 points; 2001 for Titarev-Toro).
+PAPER_1D = {
+    "sod": dict(domain=(0.0, 10.0), x_jump=5.0, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1),
+                t_end=2.0, n=201),
+    "lax": dict(domain=(0.0, 1.0), x_jump=0.5, left=(0.445, 0.698, 3.528),
+                right=(0.5, 0.0, 0.571), t_end=0.15, n=201),
+    "shu_osher": dict(domain=(0.0, 10.0), x_jump=1.0, left=(3.857143, 2.629369, 10.3333),
+                      right="shu_osher", t_end=1.8, n=201),
+    "titarev_toro": dict(domain=(0.0, 10.0), x_jump=3.5, left=(1.515695, 0.523346, 1.805),
+                         right="titarev_toro", t_end=4.0, n=2001),
+}
+
+
+def paper_problem(name, n=None, gamma=GAMMA):
+    """One of the paper's 1D Euler problems (Sec. 4.2, eq. 33-36) on n points
+    (default: the paper's).  x <= x_jump takes the left state.  Returns
+    (prob, U, meta) with meta = {x, t_end}."""
+    c = PAPER_1D[name]
+    n = c["n"] if n is None else n
+    x0, x1 = c["domain"]
+    x, h = node_coords(n, x1 - x0, x0, False)
+    left = x <= c["x_jump"]
+    rl, ul, pl = c["left"]
+    if c["right"] == "shu_osher":
+        rr, ur, pr = 1.0 + 0.2 * np.sin(5.0 * x), 0.0, 1.0
+    elif c["right"] == "titarev_toro":
+        rr, ur, pr = 1.0 + 0.1 * np.sin(20.0 * np.pi * x), 0.0, 1.0
+    else:
+        rr, ur, pr = c["right"]
+    rho = np.where(left, rl, rr)
+    u = np.where(left, ul, ur)
+    p = np.where(left, pl, pr)
+    U = prim_to_cons(rho, [u], p, gamma)
+    prob = dict(system="euler", ndim=1, n=(n,), h=(h,), bc="transmissive", gamma=gamma)
+    return prob, np.ascontiguousarray(U), dict(x=x, t_end=c["t_end"])
+
+
 # ---------------------------------------------------------------- config 3 --
 def riemann2d(seed=0, n=2048, split=0.8, gamma=GAMMA):
     """Four-quadrant 2D Riemann problem on [0, 1]^2, quadrant lines x = y =
