@@ -129,6 +129,19 @@ wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* 
 wcns_status wcns_rk4_step(wcns_plan* plan, double* U, void* work, const double* dt_dev,
                           double cfl, int32_t* status_dev, void* stream);
 
+/* Statistics of the nonlinear weights (App. A): adds to hist the counts of
+   every interpolation one residual evaluation of U performs (each
+   direction, each distinct midpoint the difference reads, each field, the
+   left and the mirrored right stencil).  hist is a device array of
+   3 x 3 x nbins uint64 counters, [kind][k][bin], kind 0 = the normalised
+   JS/Z weights omega_k, kind 1 = their FE images g_k(omega_k) / sum_l
+   g_l(omega_l), kind 2 = the weights the plan's scheme uses (PFE: after the
+   switch); bin b covers [b/nbins, (b+1)/nbins) (1.0 in the last bin).  The
+   caller zeroes hist; counts accumulate over calls.  nbins in [1, 2^24].
+   A diagnostic pass (atomics), not part of the residual. */
+wcns_status wcns_weight_histogram(wcns_plan* plan, const double* U, uint64_t* hist,
+                                  int32_t nbins, void* stream);
+
 /* Ubar += (dL/dU)^T Rbar at state U: the exact vector-Jacobian product of
    the residual, including the weights, the FE mapping, the Roe-averaged
    projection and the flux (conventions at non-smooth points: d|x|/dx = 0

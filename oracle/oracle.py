@@ -75,6 +75,8 @@ def lib(variant: str = "plain"):
         L.ora_run_to_time.argtypes = [D, P, C.c_double, C.c_double, C.c_int64,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.ora_rk4_step.argtypes = [D, P, C.c_double]
+        L.ora_interpolation_weights.argtypes = [D, P, P, C.c_int64]
+        L.ora_interpolation_weights.restype = C.c_int64
         L.ora_run_to_time_rk.argtypes = [D, P, C.c_double, C.c_double, C.c_int64, C.c_int,
                                          C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.ora_interpolate.argtypes = [D, P, P, P]
@@ -184,6 +186,15 @@ class Problem:
         U = self._u(U).copy()
         bad = lib(self.variant).ora_rk4_step(self._ref(), _p(U), dt)
         return U, bad
+
+    def interpolation_weights(self, U):
+        """(n_interp, 3, 3): per interpolation of one residual evaluation, the
+        JS/Z weights, their renormalised FE images and the weights used."""
+        U = self._u(U)
+        n = lib(self.variant).ora_interpolation_weights(self._ref(), _p(U), None, 0)
+        out = np.empty((n, 3, 3))
+        lib(self.variant).ora_interpolation_weights(self._ref(), _p(U), _p(out), n)
+        return out
 
     def run_to_time(self, U, t_end, cfl=0.5, max_steps=10**9, method="rk3"):
         """March to t_end (last step clipped) with SSP-RK3 or the RK4 of eq. 16."""

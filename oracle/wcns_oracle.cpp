@@ -511,6 +511,78 @@ void residual(const Desc& D, const T* U, T* R) {
   }
 }
 
+// ------------------------------------------------- weight statistics -------
+// Every interpolation one residual evaluation performs (App. A statistics):
+// for each direction, line, distinct midpoint (periodic: N per line;
+// transmissive: the N + 2G - 5 the difference reads), field and side (left,
+// then mirrored right), nine values: the normalised JS/Z weights, their FE
+// images g_k(omega_k) / sum_l g_l(omega_l), and the weights the configured
+// scheme uses.  Returns the number of interpolations written (at most cap).
+inline int64_t interpolation_weights(const Desc& D, const double* U, double* out, int64_t cap) {
+  const int nv = nvars(D);
+  const int64_t np = npoints(D);
+  const int G = ghosts(D);
+  int64_t count = 0;
+  for (int d = 0; d < D.ndim; ++d) {
+    const int64_t N = D.n[d];
+    const int64_t stride = (d == 0) ? 1 : (d == 1) ? D.n[0] : D.n[0] * D.n[1];
+    int a1 = (d == 0) ? 1 : 0;
+    int a2 = (d == 2) ? 1 : 2;
+    const int64_t s1 = (a1 == 0) ? 1 : (a1 == 1) ? D.n[0] : D.n[0] * D.n[1];
+    const int64_t s2 = (a2 == 0) ? 1 : (a2 == 1) ? D.n[0] : D.n[0] * D.n[1];
+    std::vector<double> line((N + 2 * G) * nv);
+    for (int64_t i2 = 0; i2 < D.n[a2]; ++i2)
+      for (int64_t i1 = 0; i1 < D.n[a1]; ++i1) {
+        const int64_t base = i1 * s1 + i2 * s2;
+        for (int64_t j = -G; j < N + G; ++j) {
+          int64_t src = (D.bc[d] == 0) ? ((j % N) + N) % N : ((j < 0) ? 0 : (j >= N ? N - 1 : j));
+          for (int v = 0; v < nv; ++v) line[(j + G) * nv + v] = U[v * np + base + src * stride];
+        }
+        const int64_t mlo = (D.bc[d] == 0) ? 0 : -G + 2;
+        const int64_t mhi = (D.bc[d] == 0) ? N - 1 : N + G - 4;
+        for (int64_t m = mlo; m <= mhi; ++m) {
+          const double* st[6];
+          for (int k = 0; k < 6; ++k) st[k] = &line[(m - 2 + k + G) * nv];
+          double W[6][5];
+          if (D.system == 1 && D.charproj) {
+            double Lm[5][5], Rm[5][5];
+            euler_eigenvectors(D.ndim, d, D.gamma, st[2], st[3], Lm, Rm);
+            for (int j = 0; j < 6; ++j)
+              for (int r = 0; r < nv; ++r) {
+                double acc = 0.0;
+                for (int c = 0; c < nv; ++c) acc = acc + Lm[r][c] * st[j][c];
+                W[j][r] = acc;
+              }
+          } else {
+            for (int j = 0; j < 6; ++j)
+              for (int r = 0; r < nv; ++r) W[j][r] = st[j][r];
+          }
+          for (int r = 0; r < nv; ++r)
+            for (int side = 0; side < 2; ++side) {
+              double sten[5];
+              for (int k = 0; k < 5; ++k) sten[k] = side == 0 ? W[k][r] : W[5 - k][r];
+              double wb[3], wo[3], g[3], gs = 0.0;
+              interpolate(D, sten, wb, wo);
+              for (int k = 0; k < 3; ++k) {
+                g[k] = fe_map(k, wb[k], D.xi, D.kappa);
+                gs = gs + g[k];
+              }
+              if (count < cap) {
+                double* o = out + 9 * count;
+                for (int k = 0; k < 3; ++k) {
+                  o[k] = wb[k];
+                  o[3 + k] = g[k] / gs;
+                  o[6 + k] = wo[k];
+                }
+              }
+              ++count;
+            }
+        }
+      }
+  }
+  return count;
+}
+
 // -------------------------------------------------------------- time step --
 // Largest stable step dt = CFL / max_i sum_d (|u_d| + c) / h_d.
 inline double cfl_dt(const Desc& D, const double* U, double cfl) {
@@ -671,6 +743,10 @@ int ora_run_to_time(const Desc* D, double* U, double cfl, double t_end, int64_t 
 }
 
 int ora_rk4_step(const Desc* D, double* U, double dt) { return ora::rk4_step(*D, U, dt); }
+
+int64_t ora_interpolation_weights(const Desc* D, const double* U, double* out, int64_t cap) {
+  return ora::interpolation_weights(*D, U, out, cap);
+}
 
 // March to t_end with the CFL step (last step clipped) by SSP-RK3 (method 3)
 // or the four-stage scheme of eq. 16 (method 4).

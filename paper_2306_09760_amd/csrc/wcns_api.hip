@@ -466,6 +466,22 @@ wcns_status wcns_rk4_step(wcns_plan* plan, double* U, void* work, const double* 
   return stage_lin(plan, U3, A, U, 1.0, 1.0 / 3.0, 1.0 / 6.0, dt, Racc, status_dev, s);
 }
 
+wcns_status wcns_weight_histogram(wcns_plan* plan, const double* U, uint64_t* hist, int32_t nbins,
+                                  void* stream) {
+  g_err.clear();
+  if (!plan || !U || !hist) return fail(WCNS_EINVAL, "NULL argument");
+  if (nbins < 1 || nbins > (1 << 24)) return fail(WCNS_EINVAL, "nbins must be in [1, 2^24]");
+  for (int d = 0; d < plan->d.ndim; ++d) {
+    SweepArgs a;
+    sweep_common(plan, d, &a);
+    a.U = U;
+    WCNS_HIP(launch_weight_hist(plan->nv, d, a, (unsigned long long*)hist, nbins,
+                                (hipStream_t)stream),
+             "weight histogram launch");
+  }
+  return WCNS_OK;
+}
+
 wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double* Rbar,
                                   double* Ubar, void* work, void* stream) {
   g_err.clear();

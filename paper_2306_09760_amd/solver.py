@@ -95,14 +95,19 @@ class Plan:
                                   _ptr(status), _stream()), "wcns_rk4_step")
         return U
 
-    def run_to_time(self, U, t_end, cfl=0.5, method="rk3", max_steps=10 ** 7, status=None):
+    def run_to_time(self, U, t_end, cfl=0.5, method="rk3", max_steps=10 ** 7, status=None,
+                    before_step=None):
         """March U in place to t_end with CFL-limited steps, the last one
         clipped to land on t_end.  The step size is read back to the host
-        once per step (to clip and count).  Returns (steps, t)."""
+        once per step (to clip and count).  before_step(U), if given, is
+        called with the state at the start of every step.  Returns
+        (steps, t)."""
         step = {"rk3": self.rk3_step, "rk4": self.rk4_step}[method]
         dt = torch.zeros(1, dtype=torch.float64, device=self.device)
         t, steps = 0.0, 0
         while t < t_end and steps < max_steps:
+            if before_step is not None:
+                before_step(U)
             self.cfl_dt(U, cfl, out=dt)
             h = float(dt.item())
             if t + h > t_end:
@@ -112,6 +117,20 @@ class Plan:
             t += h
             steps += 1
         return steps, t
+
+    def weight_histogram(self, U, hist=None, nbins=10000):
+        """Adds the weight counts of one residual evaluation of U to hist, an
+        int64 tensor (3, 3, nbins) = [kind][k][bin] (kind 0: JS/Z weights,
+        1: their FE images, 2: the weights the scheme uses); see
+        wcns_weight_histogram in include/wcns.h."""
+        self._check_state(U)
+        if hist is None:
+            hist = torch.zeros((3, 3, nbins), dtype=torch.int64, device=self.device)
+        if hist.dtype != torch.int64 or not hist.is_contiguous() or hist.numel() % 9:
+            raise _lib.WCNSError("hist must be a contiguous int64 tensor of 3 x 3 x nbins")
+        check(lib().wcns_weight_histogram(self._h, _ptr(U), _ptr(hist), hist.numel() // 9,
+                                          _stream()), "wcns_weight_histogram")
+        return hist
 
     def residual_adjoint(self, U, Rbar, Ubar=None):
         """Ubar += (dL/dU)^T Rbar (Ubar zero-initialised if None)."""
