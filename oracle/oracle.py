@@ -27,6 +27,7 @@ SYSTEMS = {"advection": 0, "euler": 1}
 BCS = {"periodic": 0, "transmissive": 1}
 WEIGHTS = {"js": 0, "z": 1, "fe": 2, "pfe": 3, "linear": 4}
 DIFFS = {"mnd6": 0, "md6": 1}
+FAMILIES = {"wcns": 0, "weno": 1}
 
 
 def build(force: bool = True) -> str:
@@ -48,7 +49,7 @@ class _Desc(C.Structure):
         ("kappa", C.c_double), ("cv", C.c_double),
         ("system", C.c_int32), ("ndim", C.c_int32), ("bc", C.c_int32 * 3),
         ("weights", C.c_int32), ("zpow", C.c_int32), ("diff", C.c_int32),
-        ("charproj", C.c_int32), ("pad_", C.c_int32),
+        ("charproj", C.c_int32), ("family", C.c_int32),
     ]
 
 
@@ -85,6 +86,10 @@ def lib(variant: str = "plain"):
         L.ora_interpolate_jvp.restype = C.c_double
         L.ora_fe_map.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double]
         L.ora_fe_map.restype = C.c_double
+        L.ora_fe_map_family.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_int]
+        L.ora_fe_map_family.restype = C.c_double
+        L.ora_reconstruct_weno.argtypes = [D, P, P, P]
+        L.ora_reconstruct_weno.restype = C.c_double
         L.ora_eigenvectors.argtypes = [C.c_int, C.c_int, C.c_double, P, P, P, P]
         L.ora_euler_flux.argtypes = [C.c_int, C.c_int, C.c_double, P, P]
         L.ora_midpoint_flux.argtypes = [D, C.c_int, P, P]
@@ -105,7 +110,7 @@ class Problem:
     def __init__(self, *, system="euler", ndim=1, n=(16,), h=None, gamma=1.4,
                  adv=(1.0, 1.0, 1.0), bc="periodic", weights="fe", zpow=2,
                  diff="mnd6", charproj=True, eps=1e-40, xi=1e6, kappa=0.5,
-                 cv=1e-3, variant="plain"):
+                 cv=1e-3, family="wcns", variant="plain"):
         n = tuple(int(v) for v in n)
         assert len(n) == ndim
         if h is None:
@@ -125,6 +130,7 @@ class Problem:
         d.zpow = zpow
         d.diff = DIFFS[diff]
         d.charproj = 1 if charproj else 0
+        d.family = FAMILIES[family]
         self.desc = d
         self.variant = variant
         self.ndim, self.n, self.h = ndim, n, h
@@ -192,6 +198,8 @@ class Problem:
         JS/Z weights, their renormalised FE images and the weights used."""
         U = self._u(U)
         n = lib(self.variant).ora_interpolation_weights(self._ref(), _p(U), None, 0)
+        if n < 0:
+            raise ValueError("weight statistics cover the WCNS family only")
         out = np.empty((n, 3, 3))
         lib(self.variant).ora_interpolation_weights(self._ref(), _p(U), _p(out), n)
         return out
@@ -210,6 +218,14 @@ class Problem:
         else:
             raise ValueError(method)
         return U, s.value, t.value, bad
+
+    def reconstruct_weno(self, f5):
+        """One WENO5 reconstruction of App. B: (value, base weights, weights used)."""
+        f5 = np.ascontiguousarray(f5, dtype=np.float64)
+        wb = np.empty(3)
+        wo = np.empty(3)
+        v = lib(self.variant).ora_reconstruct_weno(self._ref(), _p(f5), _p(wb), _p(wo))
+        return v, wb, wo
 
     def interpolate(self, u5):
         u5 = np.ascontiguousarray(u5, dtype=np.float64)
@@ -239,8 +255,11 @@ class Problem:
         return dict(zip(("add", "mul", "div", "sqrt", "tanh"), list(c)))
 
 
-def fe_map(i, w, xi, kappa=0.5):
-    return lib().ora_fe_map(i, float(w), float(xi), float(kappa))
+def fe_map(i, w, xi, kappa=0.5, family="wcns"):
+    """g_i(w) of eq. 20 with the table of Sec. 3.1 (wcns) or Table B.2 (weno)."""
+    if family == "wcns":
+        return lib().ora_fe_map(i, float(w), float(xi), float(kappa))
+    return lib().ora_fe_map_family(i, float(w), float(xi), float(kappa), FAMILIES[family])
 
 
 def eigenvectors(nd, d, gamma, Ua, Ub):

@@ -128,11 +128,13 @@ struct Desc {
   int32_t zpow;     // exponent p of eq. 14
   int32_t diff;     // 0 = MND6, 1 = MD6 (eq. 3)
   int32_t charproj; // 1 = characteristic projection, 0 = component-wise
-  int32_t pad_;
+  int32_t family;   // 0 = WCNS (interpolation + LLF + MND6/MD6),
+                    // 1 = finite-difference WENO5 of App. B (flux splitting)
 };
 
 enum { W_JS = 0, W_Z = 1, W_FE = 2, W_PFE = 3, W_LINEAR = 4 };
 enum { DIFF_MND6 = 0, DIFF_MD6 = 1 };
+enum { FAMILY_WCNS = 0, FAMILY_WENO = 1 };
 
 inline int nvars(const Desc& D) { return D.system == 0 ? 1 : D.ndim + 2; }
 inline int64_t npoints(const Desc& D) { return D.n[0] * D.n[1] * D.n[2]; }
@@ -162,16 +164,32 @@ static const MapRow map_table[3] = {
      {0.0, 5.0 / 16.0, 1.0 / 2.0, 0.0, 0.0},
      {0.0, 5.0 / 16.0, 1.0 / 3.0, 1.0, 0.0}},
 };
+// Table B.2 (App. B): the same construction for the embedded fifth-order WENO
+// scheme, whose ideal weights are (1/10, 6/10, 3/10) (Table B.1).
+static const MapRow map_table_weno[3] = {
+    {3, {true, false, false, true, false},
+     {0.0, 1.0 / 10.0, 1.0 / 4.0, 0.0, 0.0},
+     {0.0, 1.0 / 10.0, 1.0 / 7.0, 1.0, 0.0}},
+    {4, {true, false, false, false, true},
+     {0.0, 6.0 / 10.0, 1.0 / 2.0, 3.0 / 4.0, 0.0},
+     {0.0, 6.0 / 10.0, 2.0 / 3.0, 6.0 / 7.0, 1.0}},
+    {3, {true, false, false, true, false},
+     {0.0, 3.0 / 10.0, 1.0 / 2.0, 0.0, 0.0},
+     {0.0, 3.0 / 10.0, 1.0 / 3.0, 1.0, 0.0}},
+};
+static const double d_ideal_weno[3] = {1.0 / 10.0, 6.0 / 10.0, 3.0 / 10.0};
+
 // Sign table phi(i,j) of eq. 21.
 inline double phi(int i, int j) {
   if ((i == 0 && j == 3) || (i == 2 && j == 3) || (i == 1 && j == 4)) return -1.0;
   return 1.0;
 }
 
-// g_i(omega) of eq. 20.
+// g_i(omega) of eq. 20 with the coefficient table of Sec. 3.1 (family 0) or
+// Table B.2 (family 1).
 template <class T>
-T fe_map(int i, T w, double xi, double kappa) {
-  const MapRow& row = map_table[i];
+T fe_map(int i, T w, double xi, double kappa, int family = FAMILY_WCNS) {
+  const MapRow& row = family == FAMILY_WENO ? map_table_weno[i] : map_table[i];
   T g = w;
   for (int j = 1; j <= row.J; ++j) {
     T wj = row.self[j] ? w : T(row.omega[j]);
@@ -364,6 +382,74 @@ void euler_eigenvectors(int nd, int d, double gamma, const T* Ua, const T* Ub, T
   }
 }
 
+// ------------------------- WENO5 reconstruction (App. B, Jiang and Shu) --
+// Reconstructs the split flux at x_{i+1/2} from its point values f =
+// (f_{i-2}, ..., f_{i+2}): candidates of the three sub-stencils, Jiang-Shu
+// smoothness indicators, JS / Z weights with the ideal weights of Table B.1,
+// the FE mapping with Table B.2, PFE switch.  As for the WCNS indicators, the
+// one-sided differences are taken through the first differences of f.
+template <class T>
+T reconstruct_weno(const Desc& D, const T f[5], T* w_base = nullptr, T* w_out = nullptr) {
+  T df[4];
+  for (int j = 0; j < 4; ++j) df[j] = f[j + 1] - f[j];
+  // second differences and one-sided first differences of each sub-stencil
+  T s2[3], s1[3], beta[3];
+  s2[0] = df[1] - df[0];                      // f_{i-2} - 2f_{i-1} + f_i
+  s1[0] = T(3.0) * df[1] - df[0];             // f_{i-2} - 4f_{i-1} + 3f_i
+  s2[1] = df[2] - df[1];                      // f_{i-1} - 2f_i + f_{i+1}
+  s1[1] = df[1] + df[2];                      // f_{i+1} - f_{i-1}
+  s2[2] = df[3] - df[2];                      // f_i - 2f_{i+1} + f_{i+2}
+  s1[2] = T(3.0) * df[2] - df[3];             // -3f_i + 4f_{i+1} - f_{i+2}
+  for (int k = 0; k < 3; ++k)
+    beta[k] = T(13.0 / 12.0) * s2[k] * s2[k] + T(0.25) * s1[k] * s1[k];
+  T w[3];
+  if (D.weights == W_LINEAR) {
+    for (int k = 0; k < 3; ++k) w[k] = T(d_ideal_weno[k]);
+  } else if (D.weights == W_JS) {
+    T alpha[3], sum = T(0.0);
+    for (int k = 0; k < 3; ++k) {
+      T den = beta[k] + T(D.eps);
+      alpha[k] = T(d_ideal_weno[k]) / (den * den);
+      sum = sum + alpha[k];
+    }
+    for (int k = 0; k < 3; ++k) w[k] = alpha[k] / sum;
+  } else {
+    T tau = abs_(beta[0] - beta[2]);
+    T alpha[3], sum = T(0.0);
+    for (int k = 0; k < 3; ++k) {
+      T ratio = tau / (beta[k] + T(D.eps));
+      T powr = T(1.0);
+      for (int q = 0; q < D.zpow; ++q) powr = powr * ratio;
+      alpha[k] = T(d_ideal_weno[k]) * (T(1.0) + powr);
+      sum = sum + alpha[k];
+    }
+    for (int k = 0; k < 3; ++k) w[k] = alpha[k] / sum;
+  }
+  if (w_base)
+    for (int k = 0; k < 3; ++k) w_base[k] = w[k];
+  bool map = (D.weights == W_FE);
+  if (D.weights == W_PFE) {
+    bool inside = true;
+    for (int k = 0; k < 3; ++k)
+      if (!(val(w[k]) >= d_ideal_weno[k] - D.cv && val(w[k]) <= d_ideal_weno[k] + D.cv)) inside = false;
+    map = !inside;
+  }
+  if (map) {
+    T g[3], sum = T(0.0);
+    for (int k = 0; k < 3; ++k) {
+      g[k] = fe_map(k, w[k], D.xi, D.kappa, FAMILY_WENO);
+      sum = sum + g[k];
+    }
+    for (int k = 0; k < 3; ++k) w[k] = g[k] / sum;
+  }
+  if (w_out)
+    for (int k = 0; k < 3; ++k) w_out[k] = w[k];
+  T q0 = (T(2.0) * f[0] - T(7.0) * f[1] + T(11.0) * f[2]) / T(6.0);
+  T q1 = (T(-1.0) * f[1] + T(5.0) * f[2] + T(2.0) * f[3]) / T(6.0);
+  T q2 = (T(2.0) * f[2] + T(5.0) * f[3] - f[4]) / T(6.0);
+  return w[0] * q0 + w[1] * q1 + w[2] * q2;
+}
+
 // ------------------------------------------------------- midpoint flux -----
 // Numerical flux at the midpoint between nodes m and m+1 of a line in
 // direction d.  st[k] points to the nv values of node m-2+k, k = 0..5.
@@ -431,6 +517,65 @@ void midpoint_flux(const Desc& D, int d, const T* const st[6], T* Fhat) {
     Fhat[r] = T(0.5) * (FL[r] + FR[r]) - T(0.5) * alpha * (UR[r] - UL[r]);
 }
 
+// Numerical flux of the finite-difference WENO scheme (App. B) at the
+// midpoint between nodes m and m+1: Lax-Friedrichs splitting f+- = (F(U) +-
+// alpha U)/2 with alpha the largest wave speed over the six stencil nodes
+// (|c| for advection), characteristic projection with the Roe eigenvectors of
+// nodes m, m+1, f+ reconstructed from the left-biased stencil and f- from the
+// mirrored one, F = R (f+ + f-).
+template <class T>
+void midpoint_flux_weno(const Desc& D, int d, const T* const st[6], T* Fhat) {
+  const int nd = D.ndim;
+  const int nv = nvars(D);
+  if (D.system == 0) {
+    const double a = D.adv[d];
+    T fp[5], fm[5];
+    for (int k = 0; k < 5; ++k) {
+      fp[k] = T(0.5 * (a + std::fabs(a))) * st[k][0];
+      fm[k] = T(0.5 * (a - std::fabs(a))) * st[5 - k][0];
+    }
+    Fhat[0] = reconstruct_weno(D, fp) + reconstruct_weno(D, fm);
+    return;
+  }
+  T alpha = T(0.0);
+  for (int j = 0; j < 6; ++j) alpha = max_(alpha, euler_speed(nd, d, D.gamma, st[j]));
+  T Lm[5][5], Rm[5][5];
+  if (D.charproj) {
+    euler_eigenvectors(nd, d, D.gamma, st[2], st[3], Lm, Rm);
+  } else {
+    for (int r = 0; r < 5; ++r)
+      for (int c = 0; c < 5; ++c) {
+        Lm[r][c] = T(r == c ? 1.0 : 0.0);
+        Rm[r][c] = T(r == c ? 1.0 : 0.0);
+      }
+  }
+  T P[6][5], M[6][5];  // projected f+ and f- at the six nodes
+  for (int j = 0; j < 6; ++j) {
+    T F[5];
+    euler_flux(nd, d, D.gamma, st[j], F);
+    for (int r = 0; r < nv; ++r) {
+      T ap = T(0.0), am = T(0.0);
+      for (int c = 0; c < nv; ++c) {
+        ap = ap + Lm[r][c] * (F[c] + alpha * st[j][c]);
+        am = am + Lm[r][c] * (F[c] - alpha * st[j][c]);
+      }
+      P[j][r] = T(0.5) * ap;
+      M[j][r] = T(0.5) * am;
+    }
+  }
+  T G[5];
+  for (int r = 0; r < nv; ++r) {
+    T fp[5] = {P[0][r], P[1][r], P[2][r], P[3][r], P[4][r]};
+    T fm[5] = {M[5][r], M[4][r], M[3][r], M[2][r], M[1][r]};
+    G[r] = reconstruct_weno(D, fp) + reconstruct_weno(D, fm);
+  }
+  for (int r = 0; r < nv; ++r) {
+    T acc = T(0.0);
+    for (int c = 0; c < nv; ++c) acc = acc + Rm[r][c] * G[c];
+    Fhat[r] = acc;
+  }
+}
+
 // Physical flux at a node.
 template <class T>
 void node_flux(const Desc& D, int d, const T* U, T* F) {
@@ -484,7 +629,10 @@ void residual(const Desc& D, const T* U, T* R) {
         for (int64_t m = mlo; m <= mhi; ++m) {
           const T* st[6];
           for (int k = 0; k < 6; ++k) st[k] = &line[(m - 2 + k + G) * nv];
-          midpoint_flux(D, d, st, &fhat[(m + G) * nv]);
+          if (D.family == FAMILY_WENO)
+            midpoint_flux_weno(D, d, st, &fhat[(m + G) * nv]);
+          else
+            midpoint_flux(D, d, st, &fhat[(m + G) * nv]);
         }
         // Node fluxes (needed by MND6 at i-1 .. i+1).
         for (int64_t j = -1; j <= N; ++j) node_flux(D, d, &line[(j + G) * nv], &fnode[(j + G) * nv]);
@@ -494,7 +642,10 @@ void residual(const Desc& D, const T* U, T* R) {
             auto FH = [&](int64_t m) { return fhat[(m + G) * nv + v]; };  // F~_{m+1/2}
             auto FN = [&](int64_t j) { return fnode[(j + G) * nv + v]; };
             T dfdx;
-            if (D.diff == DIFF_MD6) {
+            if (D.family == FAMILY_WENO) {
+              // conservative finite difference of the WENO flux
+              dfdx = (FH(i) - FH(i - 1)) / T(h);
+            } else if (D.diff == DIFF_MD6) {
               // eq. 3
               dfdx = (T(75.0 / 64.0) * (FH(i) - FH(i - 1)) + T(-25.0 / 384.0) * (FH(i + 1) - FH(i - 2)) +
                       T(3.0 / 640.0) * (FH(i + 2) - FH(i - 3))) /
@@ -519,6 +670,7 @@ void residual(const Desc& D, const T* U, T* R) {
 // images g_k(omega_k) / sum_l g_l(omega_l), and the weights the configured
 // scheme uses.  Returns the number of interpolations written (at most cap).
 inline int64_t interpolation_weights(const Desc& D, const double* U, double* out, int64_t cap) {
+  if (D.family != FAMILY_WCNS) return -1;  // statistics of the WCNS interpolation only
   const int nv = nvars(D);
   const int64_t np = npoints(D);
   const int G = ghosts(D);
@@ -783,6 +935,15 @@ double ora_interpolate_jvp(const Desc* D, const double* u, const double* du, dou
 }
 
 double ora_fe_map(int i, double w, double xi, double kappa) { return ora::fe_map(i, w, xi, kappa); }
+
+double ora_fe_map_family(int i, double w, double xi, double kappa, int family) {
+  return ora::fe_map(i, w, xi, kappa, family);
+}
+
+// One WENO5 reconstruction of App. B from the point values f (f_{i-2..i+2}).
+double ora_reconstruct_weno(const Desc* D, const double* f, double* w_base, double* w_out) {
+  return ora::reconstruct_weno(*D, f, w_base, w_out);
+}
 
 // Roe-averaged eigenvectors (row-major 5x5 each) and flux of one state.
 void ora_eigenvectors(int nd, int d, double gamma, const double* Ua, const double* Ub, double* L,
