@@ -61,6 +61,15 @@ typedef enum {
 /* MND6: (3/2, -3/10, 1/30) midpoint-and-node difference (WCNS-MND, Sec. 1).
    MD6: eq. 3, midpoint-only (75/64, -25/384, 3/640). */
 typedef enum { WCNS_DIFF_MND6 = 0, WCNS_DIFF_MD6 = 1 } wcns_diff;
+/* WCNS: interpolation of the (characteristic) state to the midpoints, local
+   Lax-Friedrichs flux there and the MND6 / MD6 difference (Sec. 2).
+   WENO: the filtered embedded WENO scheme of App. B: finite-difference
+   WENO5 reconstruction of the Lax-Friedrichs split flux f+- = (F +- alpha U)/2
+   (alpha: largest wave speed over the six stencil nodes), ideal weights
+   (1/10, 6/10, 3/10) of Table B.1, FE map with the coefficients of Table B.2,
+   conservative difference (F_{i+1/2} - F_{i-1/2}) / h (`diff` unused).  The
+   weights, eps, xi, kappa, cv and z_power fields apply to both. */
+typedef enum { WCNS_SCHEME_WCNS = 0, WCNS_SCHEME_WENO = 1 } wcns_scheme;
 
 typedef struct wcns_desc {
   int32_t struct_size;   /* = sizeof(wcns_desc)                                */
@@ -80,6 +89,9 @@ typedef struct wcns_desc {
   double cv;             /* PFE switch value of App. A (paper: 1e-3)           */
   int32_t z_power;       /* exponent p of eq. 14, 1..4 (paper leaves it open)  */
   int32_t char_proj;     /* 1: characteristic projection, 0: component-wise    */
+  int32_t scheme;        /* wcns_scheme (residual_adjoint, rk3_step_adjoint and
+                            the batch support WCNS only: WCNS_EUNSUPPORTED)    */
+  int32_t reserved_;     /* 0                                                  */
 } wcns_desc;
 
 typedef struct wcns_plan wcns_plan;
@@ -158,7 +170,8 @@ wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lam
 
 /* Measures the candidate tile shapes of this plan's kernels on U (timed with
    HIP events; synchronises the stream) and keeps the fastest in the plan and
-   in a per-process cache keyed by shape.  U is not modified. */
+   in a per-process cache keyed by shape.  U is not modified.  A WENO plan
+   has one compiled shape: the call returns WCNS_OK and changes nothing. */
 wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, void* stream);
 /* Current tile shapes: [0] midpoints per tile of the x sweep (128 or 256);
    [1], [2] midpoints along the line and adjacent x-columns per tile of the

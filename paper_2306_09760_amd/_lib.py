@@ -20,6 +20,7 @@ SYSTEMS = {"advection": 0, "euler": 1}
 BCS = {"periodic": 0, "transmissive": 1}
 WEIGHTS = {"js": 0, "z": 1, "fe": 2, "pfe": 3, "linear": 4}
 DIFFS = {"mnd6": 0, "md6": 1}
+SCHEMES = {"wcns": 0, "weno": 1}
 
 # Every entry point declared in include/wcns.h.
 EXPORTS = [
@@ -46,7 +47,7 @@ class Desc(C.Structure):
         ("adv_speed", C.c_double * 3), ("bc", C.c_int32 * 3), ("diff", C.c_int32),
         ("gamma", C.c_double), ("eps", C.c_double), ("xi", C.c_double),
         ("kappa", C.c_double), ("cv", C.c_double), ("z_power", C.c_int32),
-        ("char_proj", C.c_int32),
+        ("char_proj", C.c_int32), ("scheme", C.c_int32), ("reserved_", C.c_int32),
     ]
 
 
@@ -114,7 +115,7 @@ def check(status: int, what: str = "") -> None:
 
 def make_desc(*, system="euler", ndim=1, n=(16,), h=None, gamma=1.4, adv=(1.0, 1.0, 1.0),
               bc="periodic", weights="fe", zpow=2, diff="mnd6", charproj=True, eps=1e-40,
-              xi=100.0, kappa=0.5, cv=1e-3) -> Desc:
+              xi=100.0, kappa=0.5, cv=1e-3, scheme="wcns") -> Desc:
     d = Desc()
     lib().wcns_desc_init(C.byref(d))
     n = tuple(int(v) for v in n)
@@ -139,4 +140,5 @@ def make_desc(*, system="euler", ndim=1, n=(16,), h=None, gamma=1.4, adv=(1.0, 1
     d.cv = cv
     d.z_power = zpow
     d.char_proj = 1 if charproj else 0
+    d.scheme = SCHEMES[scheme]
     return d

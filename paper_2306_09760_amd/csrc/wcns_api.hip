@@ -60,10 +60,14 @@ bool in_list(int v, const int* l, int n) {
 
 // Null points kappa*(psi_{i,j} + psi_{i,j-1}) of eq. 20 from the coefficient
 // table of Sec. 3.1.
-void fill_null_points(double kappa, double* nu) {
-  const double psi0[4] = {0.0, 1.0 / 16.0, 1.0 / 11.0, 1.0};
-  const double psi1[5] = {0.0, 10.0 / 16.0, 2.0 / 3.0, 10.0 / 11.0, 1.0};
-  const double psi2[4] = {0.0, 5.0 / 16.0, 1.0 / 3.0, 1.0};
+// Null points kappa (psi_{i,j} + psi_{i,j-1}) of the three maps: the psi of
+// the coefficient table of Sec. 3.1 (WCNS) or of Table B.2 (WENO).
+void fill_null_points(double kappa, int scheme, double* nu) {
+  const bool weno = scheme == WCNS_SCHEME_WENO;
+  const double psi0[4] = {0.0, weno ? 1.0 / 10.0 : 1.0 / 16.0, weno ? 1.0 / 7.0 : 1.0 / 11.0, 1.0};
+  const double psi1[5] = {0.0, weno ? 6.0 / 10.0 : 10.0 / 16.0, 2.0 / 3.0,
+                          weno ? 6.0 / 7.0 : 10.0 / 11.0, 1.0};
+  const double psi2[4] = {0.0, weno ? 3.0 / 10.0 : 5.0 / 16.0, 1.0 / 3.0, 1.0};
   int k = 0;
   for (int j = 1; j <= 3; ++j) nu[k++] = kappa * (psi0[j] + psi0[j - 1]);
   for (int j = 1; j <= 4; ++j) nu[k++] = kappa * (psi1[j] + psi1[j - 1]);
@@ -93,6 +97,10 @@ wcns_status validate(const wcns_desc* d, bool batch) {
   if (d->system == WCNS_SYS_EULER && !(d->gamma > 1.0))
     return fail(WCNS_EINVAL, "gamma must be > 1");
   if (d->char_proj != 0 && d->char_proj != 1) return fail(WCNS_EINVAL, "char_proj must be 0 or 1");
+  if (d->scheme != WCNS_SCHEME_WCNS && d->scheme != WCNS_SCHEME_WENO)
+    return fail(WCNS_EINVAL, "unknown scheme %d", d->scheme);
+  if (batch && d->scheme != WCNS_SCHEME_WCNS)
+    return fail(WCNS_EUNSUPPORTED, "the batch supports the WCNS scheme");
   for (int k = 0; k < 3; ++k) {
     if (k < d->ndim) {
       if (!batch && d->n[k] < 9) return fail(WCNS_EINVAL, "n[%d] = %lld < 9", k, (long long)d->n[k]);
@@ -116,7 +124,8 @@ void interp_params(const wcns_desc* d, InterpParams* ip) {
   ip->xi = d->xi;
   ip->cv = d->cv;
   double nu[10];
-  fill_null_points(d->kappa, nu);
+  fill_null_points(d->kappa, d->scheme, nu);
+  ip->weno = d->scheme == WCNS_SCHEME_WENO ? 1 : 0;
   ip->weights = d->weights;
   ip->zpow = d->z_power;
   // One exponential per map: reference point c_i = mean of the map's null
@@ -213,6 +222,7 @@ wcns_status sweep_common(const wcns_plan* P, int d, SweepArgs* a) {
 }
 
 hipError_t run_sweep(const wcns_plan* P, int d, SweepArgs& a, int mode, hipStream_t s) {
+  if (P->d.scheme == WCNS_SCHEME_WENO) return launch_weno_sweep(P->nv, d, a, mode, s);
   if (d == 0) return launch_sweep(P->nv, 0, a, mode, P->tm, 1, s);
   return launch_sweep(P->nv, d, a, mode, P->seg, P->bw, s);
 }
@@ -471,6 +481,8 @@ wcns_status wcns_weight_histogram(wcns_plan* plan, const double* U, uint64_t* hi
   g_err.clear();
   if (!plan || !U || !hist) return fail(WCNS_EINVAL, "NULL argument");
   if (nbins < 1 || nbins > (1 << 24)) return fail(WCNS_EINVAL, "nbins must be in [1, 2^24]");
+  if (plan->d.scheme != WCNS_SCHEME_WCNS)
+    return fail(WCNS_EUNSUPPORTED, "weight statistics cover the WCNS scheme");
   for (int d = 0; d < plan->d.ndim; ++d) {
     SweepArgs a;
     sweep_common(plan, d, &a);
@@ -487,6 +499,8 @@ wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double
   g_err.clear();
   if (!plan || !U || !Rbar || !Ubar || !work) return fail(WCNS_EINVAL, "NULL argument");
   if (Ubar == U || Ubar == Rbar) return fail(WCNS_EINVAL, "Ubar must not alias U or Rbar");
+  if (plan->d.scheme != WCNS_SCHEME_WCNS)
+    return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
   for (int d = 0; d < plan->d.ndim; ++d) {
     AdjArgs a;
     std::memset(&a, 0, sizeof a);
@@ -512,6 +526,8 @@ wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lam
                                   const double* dt_dev, void* stream) {
   g_err.clear();
   if (!plan || !Un || !lambda || !work || !dt_dev) return fail(WCNS_EINVAL, "NULL argument");
+  if (plan->d.scheme != WCNS_SCHEME_WCNS)
+    return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)work;
   const int64_t len = plan->nv * plan->npts;
@@ -552,6 +568,7 @@ wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lam
 wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, void* stream) {
   g_err.clear();
   if (!plan || !U || !work) return fail(WCNS_EINVAL, "NULL argument");
+  if (plan->d.scheme == WCNS_SCHEME_WENO) return WCNS_OK;  // one compiled tile shape
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)work;
   double* out = (double*)(w + plan->off_W1);

@@ -54,6 +54,7 @@ struct InterpParams {
   int weights;      // WJS .. WLIN
   int zpow;         // exponent p of eq. 14 (1..4)
   int shared_exp;   // 1: one exponential per map (xi * max|nu - c| < 300)
+  int weno;         // 1: K, C2 hold the Table B.2 maps (WENO family)
 };
 
 // Physics parameters of one sweep.
@@ -394,6 +395,72 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
   return w0 * c0 + w1 * c1 + w2 * c2;
 }
 
+// ----------------------------------------- WENO5 reconstruction (App. B) --
+// Ideal weights of Table B.1 and the A_j = a_j + b_j w of the three maps of
+// Table B.2 (same construction as kG0a .. kG2b).
+constexpr double E0 = 1.0 / 10.0, E1 = 6.0 / 10.0, E2 = 3.0 / 10.0;
+constexpr double kV0a[3] = {0.5 * E0, 0.5 * (0.25 - E0), -0.5 * 0.25};
+constexpr double kV0b[3] = {-0.5, 0.0, 0.5};
+constexpr double kV1a[4] = {0.5 * E1, 0.5 * (0.5 - E1), 0.5 * (0.75 - 0.5), -0.5 * 0.75};
+constexpr double kV1b[4] = {-0.5, 0.0, 0.0, 0.5};
+constexpr double kV2a[3] = {0.5 * E2, 0.5 * (0.5 - E2), -0.25};
+constexpr double kV2b[3] = {-0.5, 0.0, 0.5};
+
+// Finite-difference WENO5 reconstruction at x_{i+1/2} from the point values
+// (f_{i-2}, ..., f_{i+2}) = (a, b, c, e, f): Jiang-Shu smoothness indicators
+// (through first differences, as for the WCNS indicators), JS / Z weights
+// with the ideal weights of Table B.1, the FE map of Table B.2 (P.K and P.C2
+// hold its null points), PFE switch.
+__device__ __forceinline__ double weno5(const InterpParams& P, double a, double b, double c,
+                                        double e, double f) {
+  const double q0 = (1.0 / 6.0) * (2.0 * a - 7.0 * b + 11.0 * c);
+  const double q1 = (1.0 / 6.0) * (-b + 5.0 * c + 2.0 * e);
+  const double q2 = (1.0 / 6.0) * (2.0 * c + 5.0 * e - f);
+  if (P.weights == WLIN) return E0 * q0 + E1 * q1 + E2 * q2;
+  const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
+  const double s20 = d1 - d0, s10 = 3.0 * d1 - d0;
+  const double s21 = d2 - d1, s11 = d1 + d2;
+  const double s22 = d3 - d2, s12 = 3.0 * d2 - d3;
+  const double B0 = (13.0 / 12.0) * s20 * s20 + 0.25 * s10 * s10;
+  const double B1 = (13.0 / 12.0) * s21 * s21 + 0.25 * s11 * s11;
+  const double B2 = (13.0 / 12.0) * s22 * s22 + 0.25 * s12 * s12;
+  double a0, a1, a2;
+  if (P.weights == WJS) {
+    const double r0 = rcp(B0 + P.eps), r1 = rcp(B1 + P.eps), r2 = rcp(B2 + P.eps);
+    a0 = E0 * r0 * r0;
+    a1 = E1 * r1 * r1;
+    a2 = E2 * r2 * r2;
+  } else {
+    const double tau = __builtin_fabs(B0 - B2);
+    const double t0 = tau * rcp(B0 + P.eps), t1 = tau * rcp(B1 + P.eps), t2 = tau * rcp(B2 + P.eps);
+    double p0 = t0, p1 = t1, p2 = t2;
+    for (int k = 1; k < P.zpow; ++k) {
+      p0 *= t0;
+      p1 *= t1;
+      p2 *= t2;
+    }
+    a0 = E0 * (1.0 + p0);
+    a1 = E1 * (1.0 + p1);
+    a2 = E2 * (1.0 + p2);
+  }
+  const double inv = rcp(a0 + a1 + a2);
+  double w0 = a0 * inv, w1 = a1 * inv, w2 = a2 * inv;
+  bool map = P.weights == WFE;
+  if (P.weights == WPFE)
+    map = !(__builtin_fabs(w0 - E0) <= P.cv && __builtin_fabs(w1 - E1) <= P.cv &&
+            __builtin_fabs(w2 - E2) <= P.cv);
+  if (map) {
+    const double g0 = fe_map<3, SPEC_GENERIC>(w0, kV0a, kV0b, P.K, P.C2[0], P, nullptr);
+    const double g1 = fe_map<4, SPEC_GENERIC>(w1, kV1a, kV1b, P.K + 3, P.C2[1], P, nullptr);
+    const double g2 = fe_map<3, SPEC_GENERIC>(w2, kV2a, kV2b, P.K + 7, P.C2[2], P, nullptr);
+    const double gi = rcp(g0 + g1 + g2);
+    w0 = g0 * gi;
+    w1 = g1 * gi;
+    w2 = g2 * gi;
+  }
+  return w0 * q0 + w1 * q1 + w2 * q2;
+}
+
 // ------------------------------------------------------------------ Euler --
 // State layout in registers: [rho, m_0 .. m_{ND-1}, E].
 
@@ -645,6 +712,13 @@ __device__ __forceinline__ double wave_rate(const double* U, double gamma, const
 #pragma unroll
   for (int k = 0; k < ND; ++k) s += (__builtin_fabs(q.vel[k]) + c) * ih[k];
   return s;
+}
+
+// Wave speed |u_DIR| + c of one state along DIR.
+template <int ND, int DIR>
+__device__ __forceinline__ double dir_speed(const double* U, double gamma) {
+  const Prim<ND> q = primitives<ND>(U, gamma);
+  return __builtin_fabs(q.vel[DIR]) + __builtin_sqrt(gamma * q.p * q.ir);
 }
 
 // True if the state is finite and (Euler) rho > 0 and p > 0.

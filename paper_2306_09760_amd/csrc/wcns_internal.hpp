@@ -75,6 +75,8 @@ hipError_t launch_axpy_state(double* y, const double* x, double a, int64_t n,
 hipError_t launch_lincomb(double* out, const double* x, double ax, const double* y, double ay,
                           const double* dt, double ydt, int64_t n, hipStream_t stream);
 hipError_t launch_zero(double* y, int64_t n, hipStream_t stream);
+// The filtered embedded WENO sweep of App. B (wcns_weno.hip).
+hipError_t launch_weno_sweep(int nv, int dir, const SweepArgs& a, int mode, hipStream_t stream);
 // Weight histograms of one direction's interpolations (wcns_stats.hip).
 hipError_t launch_weight_hist(int nv, int dir, const SweepArgs& a, unsigned long long* hist,
                               int nbins, hipStream_t stream);
