@@ -24,11 +24,13 @@ from ._lib import WCNSError
 from .solver import Plan
 
 
-def run(name, weights="fe", n=None, xi=100.0, cfl=0.3, method="rk4", t_end=None, device="cuda"):
-    """March problem ``name`` to its end time (or ``t_end``).  Returns
-    (x, U, steps) with U the final conservative state on the host."""
+def run(name, weights="fe", n=None, xi=100.0, cfl=0.3, method="rk4", t_end=None, device="cuda",
+        scheme="wcns"):
+    """March problem ``name`` to its end time (or ``t_end``) with the WCNS or
+    the filtered embedded WENO (App. B) scheme.  Returns (x, U, steps) with U
+    the final conservative state on the host."""
     prob, U, meta = W.paper_problem(name, n)
-    P = Plan(device=device, **prob, weights=weights, xi=xi)
+    P = Plan(device=device, **prob, weights=weights, xi=xi, scheme=scheme)
     Ud = torch.from_numpy(U).to(P.device)
     status = torch.zeros(1, dtype=torch.int32, device=P.device)
     steps, _ = P.run_to_time(Ud, meta["t_end"] if t_end is None else t_end, cfl=cfl,
@@ -39,17 +41,17 @@ def run(name, weights="fe", n=None, xi=100.0, cfl=0.3, method="rk4", t_end=None,
 
 
 def compare(name, weights=("js", "z", "fe", "pfe"), n=None, ref_factor=10, xi=100.0,
-            device="cuda"):
-    """L1 density distance of each weight choice from a FE run on
+            device="cuda", scheme="wcns"):
+    """L1 density distance of each weight choice from a WCNS-FE run on
     ``ref_factor`` times as many intervals (coarse nodes coincide with every
     ref_factor-th fine node)."""
     n = W.PAPER_1D[name]["n"] if n is None else n
     nref = (n - 1) * ref_factor + 1
     _, Uref, _ = run(name, "fe", nref, xi=xi, device=device)
     rho_ref = Uref[0, ::ref_factor]
-    out = {"problem": name, "points": n, "reference_points": nref, "schemes": {}}
+    out = {"problem": name, "scheme": scheme, "points": n, "reference_points": nref, "schemes": {}}
     for wname in weights:
-        x, U, steps = run(name, wname, n, xi=xi, device=device)
+        x, U, steps = run(name, wname, n, xi=xi, device=device, scheme=scheme)
         out["schemes"][wname] = {"l1_density": float(np.mean(np.abs(U[0] - rho_ref))),
                                  "steps": steps}
     return out
@@ -111,6 +113,8 @@ def main():
     ap.add_argument("--problem", default="all", choices=["all", *W.PAPER_1D])
     ap.add_argument("--weights", default="js,z,fe,pfe")
     ap.add_argument("--xi", type=float, default=100.0)
+    ap.add_argument("--scheme", default="wcns", choices=["wcns", "weno"],
+                    help="WCNS (Sec. 2) or the filtered embedded WENO of App. B")
     ap.add_argument("--stats", action="store_true",
                     help="App. A weight statistics for c_v = 0, 1e-4, 1e-3, 1e-2 instead "
                          "(at --xi; 1e6 reproduces the map's control values exactly)")
@@ -121,7 +125,8 @@ def main():
             for cv in (0.0, 1e-4, 1e-3, 1e-2):
                 print(json.dumps(weight_statistics(name, cv, xi=args.xi)), flush=True)
         else:
-            print(json.dumps(compare(name, tuple(args.weights.split(",")), xi=args.xi)), flush=True)
+            print(json.dumps(compare(name, tuple(args.weights.split(",")), xi=args.xi,
+                                     scheme=args.scheme)), flush=True)
 
 
 if __name__ == "__main__":
