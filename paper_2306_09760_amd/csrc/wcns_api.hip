@@ -142,6 +142,19 @@ void interp_params(const wcns_desc* d, InterpParams* ip) {
     for (int j = 0; j < count[m]; ++j) spread = std::max(spread, std::fabs(c[m] - nu[first[m] + j]));
   }
   ip->shared_exp = (d->xi * spread < 300.0) ? 1 : 0;
+  // Bound on ln of the product of the three maps' denominators in the
+  // unclamped SPEC_FE path: its largest value over the simplex of weights,
+  // taken at a vertex (w_i = 1, the other two 0).
+  auto softplus = [](double x) { return x > 30.0 ? x + std::log1p(std::exp(-x)) : std::log1p(std::exp(x)); };
+  double B = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double b = 0.0;
+    for (int m = 0; m < 3; ++m)
+      for (int j = 0; j < count[m]; ++j)
+        b += softplus(2.0 * d->xi * ((m == i ? 1.0 : 0.0) - nu[first[m] + j]));
+    B = std::max(B, b);
+  }
+  ip->fast_fe = (ip->shared_exp && B < 600.0) ? 1 : 0;
   for (int m = 0; m < 3; ++m) {
     ip->C2[m] = ip->shared_exp ? 2.0 * d->xi * c[m] : 0.0;
     for (int j = 0; j < count[m]; ++j) {

@@ -55,6 +55,8 @@ struct InterpParams {
   int zpow;         // exponent p of eq. 14 (1..4)
   int shared_exp;   // 1: one exponential per map (xi * max|nu - c| < 300)
   int weno;         // 1: K, C2 hold the Table B.2 maps (WENO family)
+  int fast_fe;      // 1: shared_exp and the unclamped products of the
+                    //    SPEC_FE path stay below e^600 (see fe_map_frac)
 };
 
 // Physics parameters of one sweep.
@@ -123,8 +125,9 @@ __device__ constexpr double kExp2Tab64[64] = {
 // e^z for |z| <= 708 through the table above (Tang's method, ACM TOMS 15
 // (1989)): z = (64 m + k) ln2/64 + r with |r| <= ln2/128, reduced with a
 // 36-bit head of ln2/64 (exact for |64 m + k| < 2^17) and its tail; e^r - 1
-// from the degree-6 Taylor polynomial (truncation below 3e-20); the result
-// is 2^m (T_k + T_k (e^r - 1)).  T points to the table in LDS.
+// from the degree-5 Taylor polynomial (truncation r^6 / 720 < 3.6e-17, a
+// third of an ulp of 1); the result is 2^m (T_k + T_k (e^r - 1)).  T points
+// to the table in LDS.
 __device__ __forceinline__ double exp_tab(double z, const double* T) {
   constexpr double kInv = 0x1.71547652b82fep+6;       // 64 / ln 2
   constexpr double kHi = 0x1.62e42fefa0000p-7;        // ln2/64, 36 significant bits
@@ -134,8 +137,7 @@ __device__ __forceinline__ double exp_tab(double z, const double* T) {
   r = __builtin_fma(-n, kLo, r);
   const int ni = (int)n;
   const double t = T[ni & 63];
-  double p = 1.0 / 720.0;
-  p = __builtin_fma(p, r, 1.0 / 120.0);
+  double p = 1.0 / 120.0;
   p = __builtin_fma(p, r, 1.0 / 24.0);
   p = __builtin_fma(p, r, 1.0 / 6.0);
   p = __builtin_fma(p, r, 0.5);
@@ -207,6 +209,23 @@ constexpr double kG1b[4] = {-0.5, 0.0, 0.0, 0.5};
 constexpr double kG2a[3] = {0.5 * D2, 0.5 * (0.5 - D2), -0.25};
 constexpr double kG2b[3] = {-0.5, 0.0, 0.5};
 
+// Each map is the identity below its first null point, where every t_j is -1
+// in the limit: g = w - sum_j A_j(w) there, so the a_j and the b_j of a map
+// sum to zero and sum_j A_j(w) = 0 for every w.
+constexpr bool map_sums_vanish(const double* a, const double* b, int n) {
+  double sa = 0.0, sb = 0.0, m = 0.0;
+  for (int j = 0; j < n; ++j) {
+    sa += a[j];
+    sb += b[j];
+    m = (a[j] < 0 ? -a[j] : a[j]) > m ? (a[j] < 0 ? -a[j] : a[j]) : m;
+  }
+  return sb == 0.0 && (sa < 0 ? -sa : sa) <= 1e-15 * m;
+}
+constexpr bool kMapSumsVanish = map_sums_vanish(kG0a, kG0b, 3) &&
+                                map_sums_vanish(kG1a, kG1b, 4) &&
+                                map_sums_vanish(kG2a, kG2b, 3);
+static_assert(kMapSumsVanish, "the FE maps' A_j must sum to zero");
+
 template <int SPEC = SPEC_GENERIC>
 __device__ __forceinline__ double fe_g0(double w, const InterpParams& P, double* dg = nullptr) {
   return fe_map<3, SPEC>(w, kG0a, kG0b, P.K, P.C2[0], P, dg);
@@ -223,46 +242,45 @@ __device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double*
 // g(w) of one map in the form used by the forward SPEC_FE path.  With
 // t_j = tanh(xi (w - nu_j)) = 1 - 2 / D_j, D_j = 1 + q_j, q_j = E K_j:
 //   g(w) = w + sum_j A_j(w) - 2 sum_j A_j(w) / D_j,
-// and the last sum is taken over the common denominator prod_j D_j, so the
-// map costs one reciprocal instead of one per term.  q_j is clamped above at
-// e^45, where the term contributes exactly what t_j = +1 does (A_j / D_j
-// rounds away against the other terms) and products of up to four D_j stay
-// below e^180; below e^-45, D_j = 1 + q_j rounds to 1 (t_j = -1) by itself.
+// taken over the common denominator prod_j D_j: the map returns the
+// numerator and leaves the denominator in *den, so that the caller can
+// normalise the three maps with one reciprocal.  The D_j are not clamped:
+// ln prod_j D_j is convex in w, so over the simplex of (w_0, w_1, w_2) the
+// product of all three maps' denominators peaks at a vertex, at
+// B = max_i [sum_j softplus(2 xi (1 - nu_ij)) + sum_{l != i, j} softplus(-2 xi nu_lj)]
+// (469 at xi = 100, kappa = 0.5).  The host selects this path only while
+// B < 600 (fast_fe), which leaves e^100 of headroom for the candidate values
+// that multiply the products; below e^-45 a q_j rounds away against 1.
 template <int NT, bool TAB>
-__device__ __forceinline__ double fe_map_fast(double w, const double (&a)[NT],
+__device__ __forceinline__ double fe_map_frac(double w, const double (&a)[NT],
                                               const double (&b)[NT], const double* K, double C2,
-                                              double xi2, const double* xt) {
+                                              double xi2, const double* xt, double* den) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
-  constexpr double kQhi = 3.4934271057485095e+19;  // e^45
-  double sa = 0.0, sb = 1.0;
-  for (int j = 0; j < NT; ++j) {
-    sa += a[j];
-    sb += b[j];
-  }
   const double z = __builtin_fma(xi2, w, -C2);
   const double E = TAB ? exp_tab(z, xt) : exp_cw(z);
-  double D[NT], A[NT];
+  double D[NT], A[NT];  // A holds -2 A_j
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    D[j] = __builtin_fmin(E * K[j], kQhi) + 1.0;
-    A[j] = __builtin_fma(b[j], w, a[j]);
+    D[j] = __builtin_fma(E, K[j], 1.0);
+    A[j] = __builtin_fma(-2.0 * b[j], w, -2.0 * a[j]);
   }
-  double num, den;
+  double num;
   const double d01 = D[0] * D[1];
   const double n01 = __builtin_fma(A[0], D[1], A[1] * D[0]);
   if constexpr (NT == 3) {
     num = __builtin_fma(n01, D[2], A[2] * d01);
-    den = d01 * D[2];
+    *den = d01 * D[2];
   } else {
     const double d23 = D[2] * D[3];
     const double n23 = __builtin_fma(A[2], D[3], A[3] * D[2]);
     num = __builtin_fma(n01, d23, n23 * d01);
-    den = d01 * d23;
+    *den = d01 * d23;
   }
-  return __builtin_fma(-2.0 * num, rcp(den), __builtin_fma(sb, w, sa));
+  // sum_j A_j(w) = 0 for every map (kMapSumsVanish), so g = w - 2 sum_j A_j / D_j.
+  return __builtin_fma(w, *den, num);
 }
 
-// fe_map_fast together with g'(w) = 1 + sum_j [b_j t_j + xi A_j (1 - t_j^2)],
+// g(w) of fe_map_frac together with g'(w) = 1 + sum_j [b_j t_j + xi A_j (1 - t_j^2)],
 // where t_j = 1 - 2 / D_j and 1 - t_j^2 = 4 (1 / D_j)(1 - 1 / D_j); the
 // 1 / D_j come from the one reciprocal of prod_j D_j.
 template <int NT, bool TAB = false>
@@ -276,7 +294,7 @@ __device__ __forceinline__ double fe_map_fast_d(double w, const double (&a)[NT],
   double D[NT], A[NT], o[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    D[j] = __builtin_fmin(E * K[j], kQhi) + 1.0;
+    D[j] = __builtin_fmin(__builtin_fma(E, K[j], 1.0), kQhi);
     A[j] = __builtin_fma(b[j], w, a[j]);
   }
   // o[j] = prod_{k != j} D_k
@@ -350,11 +368,14 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
     const double z2 = D2 * (q2 + t2) * (q0 * q1);
     const double zi = rcp(z0 + z1 + z2);
     const double xi2 = 2.0 * P.xi;
-    const double g0 = fe_map_fast<3, TAB>(z0 * zi, kG0a, kG0b, P.K, P.C2[0], xi2, xt);
-    const double g1 = fe_map_fast<4, TAB>(z1 * zi, kG1a, kG1b, P.K + 3, P.C2[1], xi2, xt);
-    const double g2 = fe_map_fast<3, TAB>(z2 * zi, kG2a, kG2b, P.K + 7, P.C2[2], xi2, xt);
-    const double gi = rcp(g0 + g1 + g2);
-    return (g0 * c0 + g1 * c1 + g2 * c2) * gi;
+    // g_k = n_k / e_k; the normalised weights g_k / sum_l g_l over the
+    // common denominator e_0 e_1 e_2 (below e^B, fe_map_frac): one reciprocal.
+    double e0, e1, e2;
+    const double n0 = fe_map_frac<3, TAB>(z0 * zi, kG0a, kG0b, P.K, P.C2[0], xi2, xt, &e0);
+    const double n1 = fe_map_frac<4, TAB>(z1 * zi, kG1a, kG1b, P.K + 3, P.C2[1], xi2, xt, &e1);
+    const double n2 = fe_map_frac<3, TAB>(z2 * zi, kG2a, kG2b, P.K + 7, P.C2[2], xi2, xt, &e2);
+    const double T0 = n0 * (e1 * e2), T1 = n1 * (e0 * e2), T2 = n2 * (e0 * e1);
+    return (T0 * c0 + T1 * c1 + T2 * c2) * rcp(T0 + T1 + T2);
   }
   double a0, a1, a2;
   if (!FE && P.weights == WJS) {

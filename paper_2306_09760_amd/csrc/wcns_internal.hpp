@@ -15,7 +15,7 @@ enum SweepMode : int { MODE_RES = 0, MODE_ACC = 1, MODE_STAGE = 2, MODE_LIN = 3 
 
 // Which compiled specialisation of the interpolation serves these parameters.
 inline int spec_of(const InterpParams& ip) {
-  return (ip.weights == WFE && ip.zpow == 2 && ip.shared_exp) ? SPEC_FE : SPEC_GENERIC;
+  return (ip.weights == WFE && ip.zpow == 2 && ip.fast_fe) ? SPEC_FE : SPEC_GENERIC;
 }
 
 // Arguments of one directional sweep.
