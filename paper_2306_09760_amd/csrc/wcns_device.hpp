@@ -327,33 +327,14 @@ __device__ __forceinline__ double fe_map_fast_d(double w, const double (&a)[NT],
   return g;
 }
 
-// Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
-// u_{i+2}) = (a, b, c, e, f).
+// The nonlinear weights of eq. 11 / 14 (+ FE map, eq. 20; PFE switch) from
+// the smoothness indicators, applied to the candidates (c0, c1, c2) of eq. 5.
 // xt: the kExp2Tab64 table in LDS (TAB = true), else unused.
 template <int SPEC = SPEC_GENERIC, bool TAB = false>
-__device__ __forceinline__ double interp5(const InterpParams& P, double a, double b, double c,
-                                          double e, double f, const double* xt = nullptr) {
+__device__ __forceinline__ double weigh5(const InterpParams& P, double c0, double c1, double c2,
+                                         double IS0, double IS1, double IS2,
+                                         const double* xt = nullptr) {
   constexpr bool FE = (SPEC == SPEC_FE);
-  // Candidates, eq. 5.
-  const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
-  const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
-  const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
-  if (!FE && P.weights == WLIN) return D0 * c0 + D1 * c1 + D2 * c2;
-
-  // Smoothness indicators, eq. 9-10, written through the first differences of
-  // the stencil so that a sub-stencil of equal values gives IS = 0 exactly
-  // (with FMA contraction too).  At steepness xi ~ 100 the FE map keeps a
-  // small weight g_0(0) on a stencil across a jump, and how that weight is
-  // renormalised depends on the ratio of the two flat stencils' weights, so
-  // flat stencils must not see rounding noise.
-  const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
-  const double f0 = 0.5 * (3.0 * d1 - d0), s0 = d1 - d0;
-  const double f1 = 0.5 * (d1 + d2), s1 = d2 - d1;
-  const double f2 = 0.5 * (3.0 * d2 - d3), s2 = d3 - d2;
-  const double IS0 = f0 * f0 + s0 * s0;
-  const double IS1 = f1 * f1 + s1 * s1;
-  const double IS2 = f2 * f2 + s2 * s2;
-
   if constexpr (FE) {
     // Z weights (p = 2) over the common denominator: alpha_k (IS_0 + eps)^2
     // (IS_1 + eps)^2 (IS_2 + eps)^2 = d_k ((IS_k + eps)^2 + tau^2) times the
@@ -414,6 +395,66 @@ __device__ __forceinline__ double interp5(const InterpParams& P, double a, doubl
     w2 = g2 * ginv;
   }
   return w0 * c0 + w1 * c1 + w2 * c2;
+}
+
+// Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
+// u_{i+2}) = (a, b, c, e, f).
+template <int SPEC = SPEC_GENERIC, bool TAB = false>
+__device__ __forceinline__ double interp5(const InterpParams& P, double a, double b, double c,
+                                          double e, double f, const double* xt = nullptr) {
+  constexpr bool FE = (SPEC == SPEC_FE);
+  // Candidates, eq. 5.
+  const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
+  const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
+  const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
+  if (!FE && P.weights == WLIN) return D0 * c0 + D1 * c1 + D2 * c2;
+
+  // Smoothness indicators, eq. 9-10, written through the first differences of
+  // the stencil so that a sub-stencil of equal values gives IS = 0 exactly
+  // (with FMA contraction too).  At steepness xi ~ 100 the FE map keeps a
+  // small weight g_0(0) on a stencil across a jump, and how that weight is
+  // renormalised depends on the ratio of the two flat stencils' weights, so
+  // flat stencils must not see rounding noise.
+  const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
+  const double f0 = 0.5 * (3.0 * d1 - d0), s0 = d1 - d0;
+  const double f1 = 0.5 * (d1 + d2), s1 = d2 - d1;
+  const double f2 = 0.5 * (3.0 * d2 - d3), s2 = d3 - d2;
+  return weigh5<SPEC, TAB>(P, c0, c1, c2, f0 * f0 + s0 * s0, f1 * f1 + s1 * s1,
+                           f2 * f2 + s2 * s2, xt);
+}
+
+// Both interpolations of one field at x_{m+1/2} from the six values
+// u[j] = u_{m-2+j}: the left-biased one from (u_0 .. u_4) and the right-biased
+// one from the mirrored stencil (u_5, u_4, u_3, u_2, u_1).  The mirrored
+// stencil's first differences are the negated left ones (plus u_5 - u_4), so
+// its second differences s'_1, s'_2 are the left s_2, s_1 and each of its
+// indicators equals what interp5 computes on the mirrored stencil.
+template <int SPEC = SPEC_GENERIC, bool TAB = false>
+__device__ __forceinline__ void interp5_pair(const InterpParams& P, const double (&u)[6],
+                                             double* left, double* right,
+                                             const double* xt = nullptr) {
+  constexpr bool FE = (SPEC == SPEC_FE);
+  const double c0 = 0.125 * (3.0 * u[0] - 10.0 * u[1] + 15.0 * u[2]);
+  const double c1 = 0.125 * (-u[1] + 6.0 * u[2] + 3.0 * u[3]);
+  const double c2 = 0.125 * (3.0 * u[2] + 6.0 * u[3] - u[4]);
+  const double r0 = 0.125 * (3.0 * u[5] - 10.0 * u[4] + 15.0 * u[3]);
+  const double r1 = 0.125 * (-u[4] + 6.0 * u[3] + 3.0 * u[2]);
+  const double r2 = 0.125 * (3.0 * u[3] + 6.0 * u[2] - u[1]);
+  if (!FE && P.weights == WLIN) {
+    *left = D0 * c0 + D1 * c1 + D2 * c2;
+    *right = D0 * r0 + D1 * r1 + D2 * r2;
+    return;
+  }
+  const double d0 = u[1] - u[0], d1 = u[2] - u[1], d2 = u[3] - u[2], d3 = u[4] - u[3],
+               d4 = u[5] - u[4];
+  const double s0 = d1 - d0, s1 = d2 - d1, s2 = d3 - d2, s3 = d4 - d3;
+  const double q1 = s1 * s1, q2 = s2 * s2;
+  const double f0 = 0.5 * (3.0 * d1 - d0), f1 = 0.5 * (d1 + d2), f2 = 0.5 * (3.0 * d2 - d3);
+  const double g0 = 0.5 * (3.0 * d3 - d4), g1 = 0.5 * (d2 + d3), g2 = 0.5 * (3.0 * d2 - d1);
+  *left = weigh5<SPEC, TAB>(P, c0, c1, c2, __builtin_fma(s0, s0, f0 * f0),
+                            __builtin_fma(f1, f1, q1), __builtin_fma(f2, f2, q2), xt);
+  *right = weigh5<SPEC, TAB>(P, r0, r1, r2, __builtin_fma(s3, s3, g0 * g0),
+                             __builtin_fma(g1, g1, q2), __builtin_fma(g2, g2, q1), xt);
 }
 
 // ----------------------------------------- WENO5 reconstruction (App. B) --

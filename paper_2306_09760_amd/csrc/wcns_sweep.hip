@@ -142,64 +142,46 @@ __global__ void __launch_bounds__(256) sweep_kernel(SweepArgs a, BatchArgs b, Ti
     }
   }
 
-  // one interpolation per task
+  // one field of one midpoint per task: its left- and right-biased
+  // interpolations share the six projected stencil values
 #pragma unroll 1
-  for (int q = tid; q < 2 * NV * TMW; q += NT) {
-    const int slot = q >> LTMW;
+  for (int q = tid; q < NV * TMW; q += NT) {
+    const int v = q >> LTMW;
     const int rem = q & (TMW - 1);  // = m W + c
-    const int side = slot >= NV;
-    const int v = side ? slot - NV : slot;
     const double* u = sU + rem;     // node m of column c; node m + j at u[j W]
-    double w[5];
+    double w[6];
     if (proj) {
       if constexpr (NV > 1) {
         const double* r = sR + rem;
-        // stencil value s5 sits at LDS node s5 (left) or 5 - s5 (mirrored right)
-        auto gather = [&](auto sidec) {
-          constexpr int SD = decltype(sidec)::value;
-          if (v >= 2 && v < NV - 1) {  // shear field: m_ax - vel_ax rho
-            const int ax = tangential_axis<ND, DIR>(v - 2);
-            const double va = r[ax * TMW];
-            const double* um = u + (1 + ax) * SV;
+        if (v >= 2 && v < NV - 1) {  // shear field: m_ax - vel_ax rho
+          const int ax = tangential_axis<ND, DIR>(v - 2);
+          const double va = r[ax * TMW];
+          const double* um = u + (1 + ax) * SV;
 #pragma unroll
-            for (int s5 = 0; s5 < 5; ++s5) {
-              const int k = (SD ? 5 - s5 : s5) * W;
-              w[s5] = __builtin_fma(-va, u[k], um[k]);
-            }
-          } else {
-            RoeState<ND> rs;
+          for (int j = 0; j < 6; ++j) w[j] = __builtin_fma(-va, u[j * W], um[j * W]);
+        } else {
+          RoeState<ND> rs;
 #pragma unroll
-            for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
-            rs.ic = r[(ND + 2) * TMW];
-            roe_derived<ND>(rs, a.pp.gamma);
-            double l[NV];
-            field_row<ND, DIR>(rs, v, l);
+          for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
+          rs.ic = r[(ND + 2) * TMW];
+          roe_derived<ND>(rs, a.pp.gamma);
+          double l[NV];
+          field_row<ND, DIR>(rs, v, l);
 #pragma unroll
-            for (int s5 = 0; s5 < 5; ++s5) {
-              const int k = (SD ? 5 - s5 : s5) * W;
-              double acc = l[0] * u[k];
+          for (int j = 0; j < 6; ++j) {
+            double acc = l[0] * u[j * W];
 #pragma unroll
-              for (int e = 1; e < NV; ++e) acc = __builtin_fma(l[e], u[e * SV + k], acc);
-              w[s5] = acc;
-            }
+            for (int e = 1; e < NV; ++e) acc = __builtin_fma(l[e], u[e * SV + j * W], acc);
+            w[j] = acc;
           }
-        };
-        if (side)
-          gather(std::integral_constant<int, 1>{});
-        else
-          gather(std::integral_constant<int, 0>{});
+        }
       }
     } else {
       const double* uv = u + v * SV;
-      if (side == 0) {
 #pragma unroll
-        for (int s = 0; s < 5; ++s) w[s] = uv[s * W];
-      } else {
-#pragma unroll
-        for (int s = 0; s < 5; ++s) w[s] = uv[(5 - s) * W];
-      }
+      for (int j = 0; j < 6; ++j) w[j] = uv[j * W];
     }
-    sW[q] = interp5<SPEC, SPEC == SPEC_FE>(a.ip, w[0], w[1], w[2], w[3], w[4], sX);
+    interp5_pair<SPEC, SPEC == SPEC_FE>(a.ip, w, sW + q, sW + NV * TMW + q, sX);
   }
   __syncthreads();
 
