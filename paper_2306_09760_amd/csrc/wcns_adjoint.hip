@@ -198,17 +198,12 @@ __global__ void __launch_bounds__(256)
     }
   };
 
-  // forward interpolation, one task per (side, field, midpoint)
+  // forward interpolation, one task per (field, midpoint): both sides
 #pragma unroll 1
-  for (int q = tid; q < 2 * NV * TMW; q += NT) {
-    const int slot = q >> LTMW;
-    const int rem = q & (TMW - 1);
-    const int side = slot >= NV;
-    const int v = side ? slot - NV : slot;
+  for (int q = tid; q < NV * TMW; q += NT) {
     double w[6];
-    stencil(rem, v, w);
-    sW[q] = side ? interp5<SPEC, TAB>(a.ip, w[5], w[4], w[3], w[2], w[1], sX)
-                 : interp5<SPEC, TAB>(a.ip, w[0], w[1], w[2], w[3], w[4], sX);
+    stencil(q & (TMW - 1), q >> LTMW, w);
+    interp5_pair<SPEC, TAB>(a.ip, w, sW + q, sW + NV * TMW + q, sX);
   }
   __syncthreads();
 

@@ -19,6 +19,101 @@ __device__ __forceinline__ double fe_g_d(int i, double w, const InterpParams& P,
   return fe_g2<SPEC>(w, P, dg);
 }
 
+// The FE weights' part of the VJP on the forward SPEC_FE arithmetic: from
+// the indicators IS_k, the candidates c_k and the output cotangent yb, the
+// cotangents of the candidates (the weights times yb) and of the indicators.
+// Z weights z_k = Z_k / sum Z with Z_k = d_k (q_k + tau^2) prod_{l != k} q_l,
+// q_k = (IS_k + eps)^2 (polynomial in q and tau^2, so their cotangents need
+// no reciprocal); per map, with i_j = 1 / D_j = o_j / e (o_j the product of
+// the other D, e of all), g = w - 2 sum_j A_j i_j and
+// g' = 1 - 2 sum_j b_j i_j + 4 xi sum_j A_j i_j (1 - i_j).  Five
+// reciprocals: sum Z, one per map, sum g.
+template <bool TAB>
+__device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0, double c1,
+                                               double c2, double IS0, double IS1, double IS2,
+                                               double yb, double& c0b, double& c1b, double& c2b,
+                                               double& ISb0, double& ISb1, double& ISb2,
+                                               const double* xt) {
+  const double tau = __builtin_fabs(IS0 - IS2);
+  const double t2 = tau * tau;
+  const double b0 = IS0 + P.eps, b1 = IS1 + P.eps, b2 = IS2 + P.eps;
+  const double q0 = b0 * b0, q1 = b1 * b1, q2 = b2 * b2;
+  const double p12 = q1 * q2, p02 = q0 * q2, p01 = q0 * q1;
+  const double u0 = q0 + t2, u1 = q1 + t2, u2 = q2 + t2;
+  const double Z0 = D0 * u0 * p12, Z1 = D1 * u1 * p02, Z2 = D2 * u2 * p01;
+  const double zi = rcp(Z0 + Z1 + Z2);
+  const double z[3] = {Z0 * zi, Z1 * zi, Z2 * zi};
+  const double xi2 = 2.0 * P.xi, xi4 = 4.0 * P.xi;
+  double g[3], gp[3];
+  auto map = [&](auto ntc, int k, const double* av, const double* bv, const double* K, double C2) {
+    constexpr int NT = decltype(ntc)::value;
+    const double w = z[k];
+    const double E = TAB ? exp_tab(__builtin_fma(xi2, w, -C2), xt)
+                         : exp_cw(__builtin_fma(xi2, w, -C2));
+    double D[NT], o[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) D[j] = __builtin_fma(E, K[j], 1.0);
+    const double d01 = D[0] * D[1];
+    double e;
+    if constexpr (NT == 3) {
+      o[0] = D[1] * D[2];
+      o[1] = D[0] * D[2];
+      o[2] = d01;
+      e = d01 * D[2];
+    } else {
+      const double d23 = D[2] * D[3];
+      o[0] = D[1] * d23;
+      o[1] = D[0] * d23;
+      o[2] = d01 * D[3];
+      o[3] = d01 * D[2];
+      e = d01 * d23;
+    }
+    const double r = rcp(e);
+    double gk = w, dk = 1.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const double i = o[j] * r;
+      const double Ai = __builtin_fma(bv[j], w, av[j]) * i;
+      gk = __builtin_fma(-2.0, Ai, gk);
+      if (bv[j] != 0.0) dk = __builtin_fma(-2.0 * bv[j], i, dk);
+      dk = __builtin_fma(xi4 * Ai, 1.0 - i, dk);
+    }
+    g[k] = gk;
+    gp[k] = dk;
+  };
+  map(std::integral_constant<int, 3>{}, 0, kG0a, kG0b, P.K, P.C2[0]);
+  map(std::integral_constant<int, 4>{}, 1, kG1a, kG1b, P.K + 3, P.C2[1]);
+  map(std::integral_constant<int, 3>{}, 2, kG2a, kG2b, P.K + 7, P.C2[2]);
+  const double rg = rcp(g[0] + g[1] + g[2]);
+  const double w0 = g[0] * rg, w1 = g[1] * rg, w2 = g[2] * rg;
+  c0b = w0 * yb;
+  c1b = w1 * yb;
+  c2b = w2 * yb;
+  // w = g / sum g: gb_k = (wb_k - sum_l wb_l w_l) / sum g
+  const double wb0 = yb * c0, wb1 = yb * c1, wb2 = yb * c2;
+  const double sdot = wb0 * w0 + wb1 * w1 + wb2 * w2;
+  const double wb[3] = {wb0, wb1, wb2};
+  double zb[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) zb[k] = (wb[k] - sdot) * rg * gp[k];
+  // z = Z / sum Z
+  const double zdot = zb[0] * z[0] + zb[1] * z[1] + zb[2] * z[2];
+  const double Y0 = D0 * (zb[0] - zdot) * zi, Y1 = D1 * (zb[1] - zdot) * zi,
+               Y2 = D2 * (zb[2] - zdot) * zi;
+  const double qb0 = Y0 * p12 + (Y1 * u1) * q2 + (Y2 * u2) * q1;
+  const double qb1 = Y1 * p02 + (Y0 * u0) * q2 + (Y2 * u2) * q0;
+  const double qb2 = Y2 * p01 + (Y0 * u0) * q1 + (Y1 * u1) * q0;
+  const double t2b = Y0 * p12 + Y1 * p02 + Y2 * p01;
+  ISb0 = 2.0 * b0 * qb0;
+  ISb1 = 2.0 * b1 * qb1;
+  ISb2 = 2.0 * b2 * qb2;
+  const double taub = 2.0 * tau * t2b;
+  const double dd = IS0 - IS2;
+  const double sg = dd > 0.0 ? 1.0 : (dd < 0.0 ? -1.0 : 0.0);
+  ISb0 += taub * sg;
+  ISb2 -= taub * sg;
+}
+
 // Cotangent of interp5's inputs (a, b, c, e, f) for output cotangent yb;
 // accumulates into the five references.
 // xt: the kExp2Tab64 table in LDS (TAB = true, FE specialisation only).
@@ -31,7 +126,6 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
   const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
   const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
   const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
-  double w0, w1, w2;
   double c0b, c1b, c2b;
   if (!FE && P.weights == WLIN) {
     c0b = D0 * yb;
@@ -45,97 +139,95 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     const double IS0 = f0 * f0 + s0 * s0;
     const double IS1 = f1 * f1 + s1 * s1;
     const double IS2 = f2 * f2 + s2 * s2;
-    const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
-    double a0, a1, a2, tau = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
-    const int zpow = FE ? 2 : P.zpow;
-    const bool js = !FE && P.weights == WJS;
-    if (js) {
-      a0 = D0 * r0 * r0;
-      a1 = D1 * r1 * r1;
-      a2 = D2 * r2 * r2;
-    } else {
-      tau = __builtin_fabs(IS0 - IS2);
-      q0 = tau * r0;
-      q1 = tau * r1;
-      q2 = tau * r2;
-      double p0 = q0, p1 = q1, p2 = q2;
-      for (int k = 1; k < zpow; ++k) {
-        p0 *= q0;
-        p1 *= q1;
-        p2 *= q2;
-      }
-      a0 = D0 * (1.0 + p0);
-      a1 = D1 * (1.0 + p1);
-      a2 = D2 * (1.0 + p2);
-    }
-    const double inv = rcp(a0 + a1 + a2);
-    const double z0 = a0 * inv, z1 = a1 * inv, z2 = a2 * inv;
-    bool map = FE || (P.weights == WFE);
-    if (!FE && P.weights == WPFE) {
-      const bool inside = __builtin_fabs(z0 - D0) <= P.cv && __builtin_fabs(z1 - D1) <= P.cv &&
-                          __builtin_fabs(z2 - D2) <= P.cv;
-      map = !inside;
-    }
-    double zb0, zb1, zb2;
-    if (map) {
-      double d0, d1, d2, g0, g1, g2;
-      if constexpr (FE) {
-        g0 = fe_map_fast_d<3, TAB>(z0, kG0a, kG0b, P.K, P.C2[0], P.xi, &d0, xt);
-        g1 = fe_map_fast_d<4, TAB>(z1, kG1a, kG1b, P.K + 3, P.C2[1], P.xi, &d1, xt);
-        g2 = fe_map_fast_d<3, TAB>(z2, kG2a, kG2b, P.K + 7, P.C2[2], P.xi, &d2, xt);
-      } else {
-        g0 = fe_g_d<SPEC>(0, z0, P, &d0);
-        g1 = fe_g_d<SPEC>(1, z1, P, &d1);
-        g2 = fe_g_d<SPEC>(2, z2, P, &d2);
-      }
-      const double ginv = rcp(g0 + g1 + g2);
-      w0 = g0 * ginv;
-      w1 = g1 * ginv;
-      w2 = g2 * ginv;
-      const double wb0 = yb * c0, wb1 = yb * c1, wb2 = yb * c2;
-      const double sdot = wb0 * w0 + wb1 * w1 + wb2 * w2;
-      zb0 = (wb0 - sdot) * ginv * d0;
-      zb1 = (wb1 - sdot) * ginv * d1;
-      zb2 = (wb2 - sdot) * ginv * d2;
-    } else {
-      w0 = z0;
-      w1 = z1;
-      w2 = z2;
-      zb0 = yb * c0;
-      zb1 = yb * c1;
-      zb2 = yb * c2;
-    }
-    c0b = w0 * yb;
-    c1b = w1 * yb;
-    c2b = w2 * yb;
-    // z = alpha / sum(alpha)
-    const double zdot = zb0 * z0 + zb1 * z1 + zb2 * z2;
-    const double ab0 = (zb0 - zdot) * inv, ab1 = (zb1 - zdot) * inv, ab2 = (zb2 - zdot) * inv;
     double ISb0, ISb1, ISb2;
-    if (js) {
-      // alpha = d r^2, r = 1/(IS + eps): d alpha / d IS = -2 d r^3
-      ISb0 = -2.0 * D0 * r0 * r0 * r0 * ab0;
-      ISb1 = -2.0 * D1 * r1 * r1 * r1 * ab1;
-      ISb2 = -2.0 * D2 * r2 * r2 * r2 * ab2;
+    if constexpr (FE) {
+      fe_weights_vjp<TAB>(P, c0, c1, c2, IS0, IS1, IS2, yb, c0b, c1b, c2b, ISb0, ISb1, ISb2, xt);
     } else {
-      // alpha = d (1 + q^p), q = tau r
-      double dp0 = 1.0, dp1 = 1.0, dp2 = 1.0;  // d q^p / dq = p q^(p-1)
-      for (int k = 1; k < zpow; ++k) {
-        dp0 *= q0;
-        dp1 *= q1;
-        dp2 *= q2;
+      const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
+      double a0, a1, a2, w0, w1, w2, tau = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
+      const int zpow = P.zpow;
+      const bool js = P.weights == WJS;
+      if (js) {
+        a0 = D0 * r0 * r0;
+        a1 = D1 * r1 * r1;
+        a2 = D2 * r2 * r2;
+      } else {
+        tau = __builtin_fabs(IS0 - IS2);
+        q0 = tau * r0;
+        q1 = tau * r1;
+        q2 = tau * r2;
+        double p0 = q0, p1 = q1, p2 = q2;
+        for (int k = 1; k < zpow; ++k) {
+          p0 *= q0;
+          p1 *= q1;
+          p2 *= q2;
+        }
+        a0 = D0 * (1.0 + p0);
+        a1 = D1 * (1.0 + p1);
+        a2 = D2 * (1.0 + p2);
       }
-      const double qb0 = D0 * ab0 * zpow * dp0;
-      const double qb1 = D1 * ab1 * zpow * dp1;
-      const double qb2 = D2 * ab2 * zpow * dp2;
-      const double taub = qb0 * r0 + qb1 * r1 + qb2 * r2;
-      ISb0 = -qb0 * tau * r0 * r0;
-      ISb1 = -qb1 * tau * r1 * r1;
-      ISb2 = -qb2 * tau * r2 * r2;
-      const double dd = IS0 - IS2;
-      const double sg = dd > 0.0 ? 1.0 : (dd < 0.0 ? -1.0 : 0.0);
-      ISb0 += taub * sg;
-      ISb2 -= taub * sg;
+      const double inv = rcp(a0 + a1 + a2);
+      const double z0 = a0 * inv, z1 = a1 * inv, z2 = a2 * inv;
+      bool map = P.weights == WFE;
+      if (P.weights == WPFE) {
+        const bool inside = __builtin_fabs(z0 - D0) <= P.cv && __builtin_fabs(z1 - D1) <= P.cv &&
+                            __builtin_fabs(z2 - D2) <= P.cv;
+        map = !inside;
+      }
+      double zb0, zb1, zb2;
+      if (map) {
+        double d0, d1, d2;
+        const double g0 = fe_g_d<SPEC>(0, z0, P, &d0);
+        const double g1 = fe_g_d<SPEC>(1, z1, P, &d1);
+        const double g2 = fe_g_d<SPEC>(2, z2, P, &d2);
+        const double ginv = rcp(g0 + g1 + g2);
+        w0 = g0 * ginv;
+        w1 = g1 * ginv;
+        w2 = g2 * ginv;
+        const double wb0 = yb * c0, wb1 = yb * c1, wb2 = yb * c2;
+        const double sdot = wb0 * w0 + wb1 * w1 + wb2 * w2;
+        zb0 = (wb0 - sdot) * ginv * d0;
+        zb1 = (wb1 - sdot) * ginv * d1;
+        zb2 = (wb2 - sdot) * ginv * d2;
+      } else {
+        w0 = z0;
+        w1 = z1;
+        w2 = z2;
+        zb0 = yb * c0;
+        zb1 = yb * c1;
+        zb2 = yb * c2;
+      }
+      c0b = w0 * yb;
+      c1b = w1 * yb;
+      c2b = w2 * yb;
+      // z = alpha / sum(alpha)
+      const double zdot = zb0 * z0 + zb1 * z1 + zb2 * z2;
+      const double ab0 = (zb0 - zdot) * inv, ab1 = (zb1 - zdot) * inv, ab2 = (zb2 - zdot) * inv;
+      if (js) {
+        // alpha = d r^2, r = 1/(IS + eps): d alpha / d IS = -2 d r^3
+        ISb0 = -2.0 * D0 * r0 * r0 * r0 * ab0;
+        ISb1 = -2.0 * D1 * r1 * r1 * r1 * ab1;
+        ISb2 = -2.0 * D2 * r2 * r2 * r2 * ab2;
+      } else {
+        // alpha = d (1 + q^p), q = tau r
+        double dp0 = 1.0, dp1 = 1.0, dp2 = 1.0;  // d q^p / dq = p q^(p-1)
+        for (int k = 1; k < zpow; ++k) {
+          dp0 *= q0;
+          dp1 *= q1;
+          dp2 *= q2;
+        }
+        const double qb0 = D0 * ab0 * zpow * dp0;
+        const double qb1 = D1 * ab1 * zpow * dp1;
+        const double qb2 = D2 * ab2 * zpow * dp2;
+        const double taub = qb0 * r0 + qb1 * r1 + qb2 * r2;
+        ISb0 = -qb0 * tau * r0 * r0;
+        ISb1 = -qb1 * tau * r1 * r1;
+        ISb2 = -qb2 * tau * r2 * r2;
+        const double dd = IS0 - IS2;
+        const double sg = dd > 0.0 ? 1.0 : (dd < 0.0 ? -1.0 : 0.0);
+        ISb0 += taub * sg;
+        ISb2 -= taub * sg;
+      }
     }
     const double f0b = 2.0 * f0 * ISb0, s0b = 2.0 * s0 * ISb0;
     const double f1b = 2.0 * f1 * ISb1, s1b = 2.0 * s1 * ISb1;

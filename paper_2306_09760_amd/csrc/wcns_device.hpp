@@ -280,53 +280,6 @@ __device__ __forceinline__ double fe_map_frac(double w, const double (&a)[NT],
   return __builtin_fma(w, *den, num);
 }
 
-// g(w) of fe_map_frac together with g'(w) = 1 + sum_j [b_j t_j + xi A_j (1 - t_j^2)],
-// where t_j = 1 - 2 / D_j and 1 - t_j^2 = 4 (1 / D_j)(1 - 1 / D_j); the
-// 1 / D_j come from the one reciprocal of prod_j D_j.
-template <int NT, bool TAB = false>
-__device__ __forceinline__ double fe_map_fast_d(double w, const double (&a)[NT],
-                                                const double (&b)[NT], const double* K, double C2,
-                                                double xi, double* dg, const double* xt = nullptr) {
-  static_assert(NT == 3 || NT == 4, "maps have three or four terms");
-  constexpr double kQhi = 3.4934271057485095e+19;  // e^45
-  const double z = __builtin_fma(2.0 * xi, w, -C2);
-  const double E = TAB ? exp_tab(z, xt) : exp_cw(z);
-  double D[NT], A[NT], o[NT];
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    D[j] = __builtin_fmin(__builtin_fma(E, K[j], 1.0), kQhi);
-    A[j] = __builtin_fma(b[j], w, a[j]);
-  }
-  // o[j] = prod_{k != j} D_k
-  const double d01 = D[0] * D[1];
-  double den;
-  if constexpr (NT == 3) {
-    o[0] = D[1] * D[2];
-    o[1] = D[0] * D[2];
-    o[2] = d01;
-    den = d01 * D[2];
-  } else {
-    const double d23 = D[2] * D[3];
-    o[0] = D[1] * d23;
-    o[1] = D[0] * d23;
-    o[2] = d01 * D[3];
-    o[3] = d01 * D[2];
-    den = d01 * d23;
-  }
-  const double r = rcp(den);
-  double g = w, d = 1.0;
-#pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    const double inv = o[j] * r;
-    const double t = __builtin_fma(-2.0, inv, 1.0);
-    g = __builtin_fma(A[j], t, g);
-    d = __builtin_fma(b[j], t, d);
-    d = __builtin_fma(4.0 * xi * A[j], inv * (1.0 - inv), d);
-  }
-  *dg = d;
-  return g;
-}
-
 // The nonlinear weights of eq. 11 / 14 (+ FE map, eq. 20; PFE switch) from
 // the smoothness indicators, applied to the candidates (c0, c1, c2) of eq. 5.
 // xt: the kExp2Tab64 table in LDS (TAB = true), else unused.
