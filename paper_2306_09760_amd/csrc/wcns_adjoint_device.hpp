@@ -73,7 +73,7 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const double i = o[j] * r;
-      const double Ai = __builtin_fma(bv[j], w, av[j]) * i;
+      const double Ai = (bv[j] == 0.0 ? av[j] : __builtin_fma(bv[j], w, av[j])) * i;
       gk = __builtin_fma(-2.0, Ai, gk);
       if (bv[j] != 0.0) dk = __builtin_fma(-2.0 * bv[j], i, dk);
       dk = __builtin_fma(xi4 * Ai, 1.0 - i, dk);

@@ -132,10 +132,14 @@ __device__ __forceinline__ double exp_tab(double z, const double* T) {
   constexpr double kInv = 0x1.71547652b82fep+6;       // 64 / ln 2
   constexpr double kHi = 0x1.62e42fefa0000p-7;        // ln2/64, 36 significant bits
   constexpr double kLo = 0x1.cf79abc9e3b3ap-46;       // ln2/64 - kHi
-  const double n = __builtin_rint(z * kInv);
+  // z * 64/ln2 rounded to an integer by adding 1.5 * 2^52: the sum's low 32
+  // bits hold it in two's complement (|z| <= 708 keeps it below 2^17)
+  constexpr double kShift = 0x1.8p52;
+  const double sh = __builtin_fma(z, kInv, kShift);
+  const double n = sh - kShift;
   double r = __builtin_fma(-n, kHi, z);
   r = __builtin_fma(-n, kLo, r);
-  const int ni = (int)n;
+  const int ni = (int)(unsigned)__builtin_bit_cast(unsigned long long, sh);
   const double t = T[ni & 63];
   double p = 1.0 / 120.0;
   p = __builtin_fma(p, r, 1.0 / 24.0);
@@ -193,7 +197,7 @@ __device__ __forceinline__ double fe_map(double w, const double (&a)[NT], const 
     } else {
       t = tanh_sat(P.xi * (w - K[j]));
     }
-    const double A = __builtin_fma(b[j], w, a[j]);
+    const double A = b[j] == 0.0 ? a[j] : __builtin_fma(b[j], w, a[j]);
     g = __builtin_fma(A, t, g);
     if (dg) d += b[j] * t + A * P.xi * (1.0 - t * t);
   }
@@ -262,7 +266,8 @@ __device__ __forceinline__ double fe_map_frac(double w, const double (&a)[NT],
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
     D[j] = __builtin_fma(E, K[j], 1.0);
-    A[j] = __builtin_fma(-2.0 * b[j], w, -2.0 * a[j]);
+    // (constant where b_j = 0: an fma with a zero factor would not fold)
+    A[j] = b[j] == 0.0 ? -2.0 * a[j] : __builtin_fma(-2.0 * b[j], w, -2.0 * a[j]);
   }
   double num;
   const double d01 = D[0] * D[1];
@@ -281,7 +286,8 @@ __device__ __forceinline__ double fe_map_frac(double w, const double (&a)[NT],
 }
 
 // The nonlinear weights of eq. 11 / 14 (+ FE map, eq. 20; PFE switch) from
-// the smoothness indicators, applied to the candidates (c0, c1, c2) of eq. 5.
+// the smoothness indicators, applied to the candidates of eq. 5; (c0, c1, c2)
+// are eight times the candidates (the 1/8 is applied once, to the sum).
 // xt: the kExp2Tab64 table in LDS (TAB = true), else unused.
 template <int SPEC = SPEC_GENERIC, bool TAB = false>
 __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, double c1, double c2,
@@ -309,7 +315,7 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     const double n1 = fe_map_frac<4, TAB>(z1 * zi, kG1a, kG1b, P.K + 3, P.C2[1], xi2, xt, &e1);
     const double n2 = fe_map_frac<3, TAB>(z2 * zi, kG2a, kG2b, P.K + 7, P.C2[2], xi2, xt, &e2);
     const double T0 = n0 * (e1 * e2), T1 = n1 * (e0 * e2), T2 = n2 * (e0 * e1);
-    return (T0 * c0 + T1 * c1 + T2 * c2) * rcp(T0 + T1 + T2);
+    return (0.125 * (T0 * c0 + T1 * c1 + T2 * c2)) * rcp(T0 + T1 + T2);
   }
   double a0, a1, a2;
   if (!FE && P.weights == WJS) {
@@ -347,7 +353,7 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     w1 = g1 * ginv;
     w2 = g2 * ginv;
   }
-  return w0 * c0 + w1 * c1 + w2 * c2;
+  return 0.125 * (w0 * c0 + w1 * c1 + w2 * c2);
 }
 
 // Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
@@ -356,11 +362,11 @@ template <int SPEC = SPEC_GENERIC, bool TAB = false>
 __device__ __forceinline__ double interp5(const InterpParams& P, double a, double b, double c,
                                           double e, double f, const double* xt = nullptr) {
   constexpr bool FE = (SPEC == SPEC_FE);
-  // Candidates, eq. 5.
-  const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
-  const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
-  const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
-  if (!FE && P.weights == WLIN) return D0 * c0 + D1 * c1 + D2 * c2;
+  // Candidates of eq. 5, times 8.
+  const double c0 = 3.0 * a - 10.0 * b + 15.0 * c;
+  const double c1 = -b + 6.0 * c + 3.0 * e;
+  const double c2 = 3.0 * c + 6.0 * e - f;
+  if (!FE && P.weights == WLIN) return 0.125 * (D0 * c0 + D1 * c1 + D2 * c2);
 
   // Smoothness indicators, eq. 9-10, written through the first differences of
   // the stencil so that a sub-stencil of equal values gives IS = 0 exactly
@@ -387,15 +393,16 @@ __device__ __forceinline__ void interp5_pair(const InterpParams& P, const double
                                              double* left, double* right,
                                              const double* xt = nullptr) {
   constexpr bool FE = (SPEC == SPEC_FE);
-  const double c0 = 0.125 * (3.0 * u[0] - 10.0 * u[1] + 15.0 * u[2]);
-  const double c1 = 0.125 * (-u[1] + 6.0 * u[2] + 3.0 * u[3]);
-  const double c2 = 0.125 * (3.0 * u[2] + 6.0 * u[3] - u[4]);
-  const double r0 = 0.125 * (3.0 * u[5] - 10.0 * u[4] + 15.0 * u[3]);
-  const double r1 = 0.125 * (-u[4] + 6.0 * u[3] + 3.0 * u[2]);
-  const double r2 = 0.125 * (3.0 * u[3] + 6.0 * u[2] - u[1]);
+  // candidates of eq. 5 (times 8) of both stencils
+  const double c0 = 3.0 * u[0] - 10.0 * u[1] + 15.0 * u[2];
+  const double c1 = -u[1] + 6.0 * u[2] + 3.0 * u[3];
+  const double c2 = 3.0 * u[2] + 6.0 * u[3] - u[4];
+  const double r0 = 3.0 * u[5] - 10.0 * u[4] + 15.0 * u[3];
+  const double r1 = -u[4] + 6.0 * u[3] + 3.0 * u[2];
+  const double r2 = 3.0 * u[3] + 6.0 * u[2] - u[1];
   if (!FE && P.weights == WLIN) {
-    *left = D0 * c0 + D1 * c1 + D2 * c2;
-    *right = D0 * r0 + D1 * r1 + D2 * r2;
+    *left = 0.125 * (D0 * c0 + D1 * c1 + D2 * c2);
+    *right = 0.125 * (D0 * r0 + D1 * r1 + D2 * r2);
     return;
   }
   const double d0 = u[1] - u[0], d1 = u[2] - u[1], d2 = u[3] - u[2], d3 = u[4] - u[3],
