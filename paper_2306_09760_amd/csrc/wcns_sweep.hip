@@ -45,11 +45,13 @@ struct SweepLayout {
   static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
 
-// Six waves per SIMD: the compiler keeps the kernel within 80 VGPRs without
-// spilling, and the largest tile (NV = 3, 256 midpoints, 27.3 KB of LDS)
-// still fits six workgroups in a CU's 160 KB.
+// The FE specialisation runs at six waves per SIMD: the compiler keeps it
+// within 80 VGPRs without spilling, and the largest tile (NV = 3, 256
+// midpoints, 27.3 KB of LDS) still fits six workgroups in a CU's 160 KB.
+// The generic interpolation needs ~108 VGPRs and is left unconstrained
+// (capped at 80 it spills).
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_FE ? 6 : 1))) sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g,
                                                     int mode) {
   using L = SweepLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TN = L::TN, TMW = L::TMW, SV = L::SV;
