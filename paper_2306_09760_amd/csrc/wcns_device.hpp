@@ -75,6 +75,23 @@ __device__ __forceinline__ double rcp(double x) {
   return r;
 }
 
+// sqrt(x) for x = 0 or 2^-760 <= x < inf (densities, pressures, sound speeds
+// squared): v_rsq_f64 seed, one Goldschmidt step for sqrt and 1/(2 sqrt),
+// two Newton corrections of the root (about 1 ulp); NaN for x < 0.  Without
+// the rescaling that a full-range square root needs for tiny arguments.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = __builtin_fma(-h, g, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  double d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  d = __builtin_fma(-g, g, x);
+  g = __builtin_fma(d, h, g);
+  return x == 0.0 ? 0.0 : g;
+}
+
 // e^z for |z| <= 708 (Cody-Waite reduction z = n ln2 + r, |r| <= ln2/2, then
 // the Taylor polynomial of e^r to degree 13: truncation below 5e-18).
 __device__ __forceinline__ double exp_cw(double z) {
@@ -542,9 +559,10 @@ __device__ __forceinline__ RoeState<ND> roe_average(const double* UA, const doub
                                                     double gamma) {
   const Prim<ND> A = primitives<ND>(UA, gamma);
   const Prim<ND> B = primitives<ND>(UB, gamma);
-  const double sA = __builtin_sqrt(UA[0]), sB = __builtin_sqrt(UB[0]);
-  const double den = rcp(sA + sB);
-  const double wA = sA * den, wB = sB * den;
+  // weights sqrt(rho_A) / (sqrt(rho_A) + sqrt(rho_B)) and the same for B,
+  // through s = sqrt(rho_B / rho_A)
+  const double s = sqrt_pos(UB[0] * A.ir);
+  const double wA = rcp(1.0 + s), wB = s * wA;
   RoeState<ND> r;
   double q2 = 0.0;
 #pragma unroll
@@ -556,7 +574,7 @@ __device__ __forceinline__ RoeState<ND> roe_average(const double* UA, const doub
   const double HB = (UB[ND + 1] + B.p) * B.ir;
   r.H = wA * HA + wB * HB;
   r.q2h = 0.5 * q2;
-  r.c = __builtin_sqrt((gamma - 1.0) * (r.H - r.q2h));
+  r.c = sqrt_pos((gamma - 1.0) * (r.H - r.q2h));
   r.ic = rcp(r.c);
   r.b1 = (gamma - 1.0) * r.ic * r.ic;
   r.b2 = r.q2h * r.b1;
@@ -656,8 +674,8 @@ __device__ __forceinline__ void llf_flux(const double* UL, const double* UR, dou
   double FL[NV], FR[NV];
   const Prim<ND> L = primitives<ND>(UL, gamma);
   const Prim<ND> R = primitives<ND>(UR, gamma);
-  const double cL = __builtin_sqrt(gamma * L.p * L.ir);
-  const double cR = __builtin_sqrt(gamma * R.p * R.ir);
+  const double cL = sqrt_pos(gamma * L.p * L.ir);
+  const double cR = sqrt_pos(gamma * R.p * R.ir);
   const double lamL = __builtin_fabs(L.vel[DIR]) + cL;
   const double lamR = __builtin_fabs(R.vel[DIR]) + cR;
   const double alpha = (lamL >= lamR) ? lamL : lamR;
@@ -729,7 +747,7 @@ __device__ __forceinline__ void node_flux(const PhysParams& PP, const double (&U
 template <int ND>
 __device__ __forceinline__ double wave_rate(const double* U, double gamma, const double* ih) {
   const Prim<ND> q = primitives<ND>(U, gamma);
-  const double c = __builtin_sqrt(gamma * q.p * q.ir);
+  const double c = sqrt_pos(gamma * q.p * q.ir);
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < ND; ++k) s += (__builtin_fabs(q.vel[k]) + c) * ih[k];
@@ -740,7 +758,7 @@ __device__ __forceinline__ double wave_rate(const double* U, double gamma, const
 template <int ND, int DIR>
 __device__ __forceinline__ double dir_speed(const double* U, double gamma) {
   const Prim<ND> q = primitives<ND>(U, gamma);
-  return __builtin_fabs(q.vel[DIR]) + __builtin_sqrt(gamma * q.p * q.ir);
+  return __builtin_fabs(q.vel[DIR]) + sqrt_pos(gamma * q.p * q.ir);
 }
 
 // True if the state is finite and (Euler) rho > 0 and p > 0.
