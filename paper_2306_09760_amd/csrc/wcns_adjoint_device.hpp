@@ -114,8 +114,9 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
   ISb2 -= taub * sg;
 }
 
-// Cotangent of interp5's inputs (a, b, c, e, f) for output cotangent yb;
-// accumulates into the five references.
+// Cotangent of the inputs (a, b, c, e, f) = (u_{i-2} .. u_{i+2}) of one
+// nonlinear interpolation (the left-biased one of interp5_pair) for output
+// cotangent yb; accumulates into the five references.
 // xt: the kExp2Tab64 table in LDS (TAB = true, FE specialisation only).
 template <int SPEC = SPEC_GENERIC, bool TAB = false>
 __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, double b, double c,

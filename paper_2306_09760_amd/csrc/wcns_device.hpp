@@ -373,38 +373,17 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
   return 0.125 * (w0 * c0 + w1 * c1 + w2 * c2);
 }
 
-// Nonlinear interpolation to x_{i+1/2} from (u_{i-2}, u_{i-1}, u_i, u_{i+1},
-// u_{i+2}) = (a, b, c, e, f).
-template <int SPEC = SPEC_GENERIC, bool TAB = false>
-__device__ __forceinline__ double interp5(const InterpParams& P, double a, double b, double c,
-                                          double e, double f, const double* xt = nullptr) {
-  constexpr bool FE = (SPEC == SPEC_FE);
-  // Candidates of eq. 5, times 8.
-  const double c0 = 3.0 * a - 10.0 * b + 15.0 * c;
-  const double c1 = -b + 6.0 * c + 3.0 * e;
-  const double c2 = 3.0 * c + 6.0 * e - f;
-  if (!FE && P.weights == WLIN) return 0.125 * (D0 * c0 + D1 * c1 + D2 * c2);
-
-  // Smoothness indicators, eq. 9-10, written through the first differences of
-  // the stencil so that a sub-stencil of equal values gives IS = 0 exactly
-  // (with FMA contraction too).  At steepness xi ~ 100 the FE map keeps a
-  // small weight g_0(0) on a stencil across a jump, and how that weight is
-  // renormalised depends on the ratio of the two flat stencils' weights, so
-  // flat stencils must not see rounding noise.
-  const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
-  const double f0 = 0.5 * (3.0 * d1 - d0), s0 = d1 - d0;
-  const double f1 = 0.5 * (d1 + d2), s1 = d2 - d1;
-  const double f2 = 0.5 * (3.0 * d2 - d3), s2 = d3 - d2;
-  return weigh5<SPEC, TAB>(P, c0, c1, c2, f0 * f0 + s0 * s0, f1 * f1 + s1 * s1,
-                           f2 * f2 + s2 * s2, xt);
-}
-
-// Both interpolations of one field at x_{m+1/2} from the six values
-// u[j] = u_{m-2+j}: the left-biased one from (u_0 .. u_4) and the right-biased
-// one from the mirrored stencil (u_5, u_4, u_3, u_2, u_1).  The mirrored
-// stencil's first differences are the negated left ones (plus u_5 - u_4), so
-// its second differences s'_1, s'_2 are the left s_2, s_1 and each of its
-// indicators equals what interp5 computes on the mirrored stencil.
+// Both nonlinear interpolations (eq. 5-6) of one field at x_{m+1/2} from the
+// six values u[j] = u_{m-2+j}: the left-biased one from (u_0 .. u_4) and the
+// right-biased one from the mirrored stencil (u_5, u_4, u_3, u_2, u_1).
+// Smoothness indicators (eq. 9-10) are written through the first differences
+// of the stencil so that a sub-stencil of equal values gives IS = 0 exactly
+// (with FMA contraction too): at steepness xi ~ 100 the FE map keeps a small
+// weight g_0(0) on a stencil across a jump, and how that weight is
+// renormalised depends on the ratio of the two flat stencils' weights, so
+// flat stencils must not see rounding noise.  The mirrored stencil's first
+// differences are the negated left ones (plus u_5 - u_4), so its second
+// differences s'_1, s'_2 are the left s_2, s_1.
 template <int SPEC = SPEC_GENERIC, bool TAB = false>
 __device__ __forceinline__ void interp5_pair(const InterpParams& P, const double (&u)[6],
                                              double* left, double* right,
@@ -607,24 +586,6 @@ __device__ __forceinline__ void project(const RoeState<ND>& r, const double* U, 
   W[ND + 1] = 0.5 * (theta - an);
 }
 
-// Field v of the projection of one node (row v of L applied to U); v is
-// uniform across a wavefront where this is used.
-template <int ND, int DIR>
-__device__ __forceinline__ double project_field(const RoeState<ND>& r, const double* U, int v) {
-  constexpr int NV = ND + 2;
-  if (v >= 2 && v < NV - 1) {
-    const int ax = tangential_axis<ND, DIR>(v - 2);
-    return U[1 + ax] - r.vel[ax] * U[0];
-  }
-  double um = 0.0;
-#pragma unroll
-  for (int k = 0; k < ND; ++k) um += r.vel[k] * U[1 + k];
-  const double theta = r.b2 * U[0] - r.b1 * um + r.b1 * U[ND + 1];
-  if (v == 1) return U[0] - theta;
-  const double an = (r.vel[DIR] * U[0] - U[1 + DIR]) * r.ic;
-  return (v == 0) ? 0.5 * (theta + an) : 0.5 * (theta - an);
-}
-
 // Right eigenvectors applied to characteristic values: U = R W.
 // Row v of the left eigenvector matrix L, for a field that is not a shear
 // field (v = 0, 1 or NV-1): W_v = l . U.  Same quantity as project_field,
@@ -690,45 +651,6 @@ __device__ __forceinline__ void llf_flux(const double* UL, const double* UR, dou
   FR[ND + 1] = (UR[ND + 1] + R.p) * R.vel[DIR];
 #pragma unroll
   for (int v = 0; v < NV; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * alpha * (UR[v] - UL[v]);
-}
-
-// Numerical flux at the midpoint between nodes s[2] and s[3] of a six-node
-// stencil s[0..5] (nodes m-2 .. m+3) along DIR.  NV = 1: scalar advection.
-template <int NV, int DIR, int SPEC = SPEC_GENERIC>
-__device__ __forceinline__ void midpoint_flux(const InterpParams& IP, const PhysParams& PP,
-                                              const double (&s)[6][NV], double (&F)[NV]) {
-  if constexpr (NV == 1) {
-    const double uL = interp5<SPEC>(IP, s[0][0], s[1][0], s[2][0], s[3][0], s[4][0]);
-    const double uR = interp5<SPEC>(IP, s[5][0], s[4][0], s[3][0], s[2][0], s[1][0]);
-    F[0] = 0.5 * PP.adv * (uL + uR) - 0.5 * __builtin_fabs(PP.adv) * (uR - uL);
-  } else {
-    constexpr int ND = NV - 2;
-    double WL[NV], WR[NV], UL[NV], UR[NV];
-    if (PP.charproj) {
-      const RoeState<ND> r = roe_average<ND>(s[2], s[3], PP.gamma);
-      double W[6][NV];
-#pragma unroll
-      for (int j = 0; j < 6; ++j) project<ND, DIR>(r, s[j], W[j]);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        WL[v] = interp5<SPEC>(IP, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v]);
-        WR[v] = interp5<SPEC>(IP, W[5][v], W[4][v], W[3][v], W[2][v], W[1][v]);
-        // Keep the scheduler from interleaving the fields: bounded live ranges
-        // keep the kernel within 2 waves per SIMD without spills.
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      unproject<ND, DIR>(r, WL, UL);
-      unproject<ND, DIR>(r, WR, UR);
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        UL[v] = interp5<SPEC>(IP, s[0][v], s[1][v], s[2][v], s[3][v], s[4][v]);
-        UR[v] = interp5<SPEC>(IP, s[5][v], s[4][v], s[3][v], s[2][v], s[1][v]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    llf_flux<ND, DIR>(UL, UR, PP.gamma, F);
-  }
 }
 
 // Physical flux at one node along DIR.
