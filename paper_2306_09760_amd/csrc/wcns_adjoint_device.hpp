@@ -284,8 +284,8 @@ __device__ __forceinline__ void flux_speed_vjp(const double* U, double gamma, co
   if (lamb != 0.0) {
     vnb += lamb * (vn > 0.0 ? 1.0 : (vn < 0.0 ? -1.0 : 0.0));
     const double X = gamma * p * ir;
-    const double cs = __builtin_sqrt(X);
-    const double Xb = lamb * 0.5 / cs;
+    const double cs = sqrt_pos(X);
+    const double Xb = 0.5 * lamb * rcp(cs);
     pb += Xb * gamma * ir;
     irb += Xb * gamma * p;
   }
@@ -330,7 +330,7 @@ __device__ __forceinline__ void roe_vjp(const double* UA, const double* UB, doub
   // Forward pieces of the average.
   const Prim<ND> A = primitives<ND>(UA, gamma);
   const Prim<ND> B = primitives<ND>(UB, gamma);
-  const double sA = __builtin_sqrt(UA[0]), sB = __builtin_sqrt(UB[0]);
+  const double sA = sqrt_pos(UA[0]), sB = sqrt_pos(UB[0]);
   const double den = rcp(sA + sB);
   const double wA = sA * den, wB = sB * den;
   const double HA = (UA[ND + 1] + A.p) * A.ir;
@@ -367,7 +367,7 @@ __device__ __forceinline__ void roe_vjp(const double* UA, const double* UB, doub
       irb += velb[k] * U[1 + k];
     }
     Ub[ND + 1] += Eb;
-    Ub[0] += -irb * Q.ir * Q.ir + sb * 0.5 / s;
+    Ub[0] += -irb * Q.ir * Q.ir + 0.5 * sb * rcp(s);
   };
   node(UA, A, sA, sAb, HAb, velAb, UbA);
   node(UB, B, sB, sBb, HBb, velBb, UbB);
@@ -381,8 +381,8 @@ __device__ __forceinline__ void llf_vjp(const double* UL, const double* UR, doub
   constexpr int NV = ND + 2;
   const Prim<ND> L = primitives<ND>(UL, gamma);
   const Prim<ND> R = primitives<ND>(UR, gamma);
-  const double lamL = __builtin_fabs(L.vel[DIR]) + __builtin_sqrt(gamma * L.p * L.ir);
-  const double lamR = __builtin_fabs(R.vel[DIR]) + __builtin_sqrt(gamma * R.p * R.ir);
+  const double lamL = __builtin_fabs(L.vel[DIR]) + sqrt_pos(gamma * L.p * L.ir);
+  const double lamR = __builtin_fabs(R.vel[DIR]) + sqrt_pos(gamma * R.p * R.ir);
   const bool takeL = lamL >= lamR;
   const double alpha = takeL ? lamL : lamR;
   double alphab = 0.0, Fh[NV];

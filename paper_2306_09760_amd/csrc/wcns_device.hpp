@@ -694,8 +694,9 @@ __device__ __forceinline__ bool physical(const double (&U)[NV], double gamma) {
     double mm = 0.0;
 #pragma unroll
     for (int k = 0; k < ND; ++k) mm += U[1 + k] * U[1 + k];
-    const double p = (gamma - 1.0) * (U[ND + 1] - 0.5 * mm / U[0]);
-    ok = ok && (U[0] > 0.0) && (p > 0.0);
+    // with rho > 0 and gamma > 1: p = (gamma - 1)(E - |m|^2 / (2 rho)) > 0
+    // exactly when 2 E rho - |m|^2 > 0
+    ok = ok && (U[0] > 0.0) && (__builtin_fma(2.0 * U[ND + 1], U[0], -mm) > 0.0);
   }
   return ok;
 }
