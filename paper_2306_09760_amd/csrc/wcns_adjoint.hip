@@ -110,16 +110,35 @@ __global__ void __launch_bounds__(256)
   }
   const int64_t nb = i0 - 5;  // position of LDS node 0
 
-  // load
-  if constexpr (TAB) {
-    if (tid < 64) sX[tid] = kExp2Tab64[tid];
-  }
-  for (int idx = tid; idx < SV; idx += NT) {
-    const int k = idx >> LW, c = idx & (W - 1);
-    const int cc = c < ncol ? c : ncol - 1;
-    const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+  // load: all global reads of the tile issued before the first LDS write
+  constexpr int NIT = (SV + NT - 1) / NT;
+  static_assert(NIT <= 2, "a tile holds at most two nodes per lane");
+  double buf[NIT][NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) sU[v * SV + idx] = a.U[v * a.npts + gi];
+  for (int it = 0; it < NIT; ++it) {
+    const int idx = tid + it * NT;
+    if (idx < SV) {
+      const int k = idx >> LW, c = idx & (W - 1);
+      const int cc = c < ncol ? c : ncol - 1;
+      const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
+    }
+  }
+  double xv = 0.0;
+  if constexpr (TAB) {
+    if (tid < 64) xv = kExp2Tab64[tid];
+  }
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int idx = tid + it * NT;
+    if (idx < SV) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sU[v * SV + idx] = buf[it][v];
+    }
+  }
+  if constexpr (TAB) {
+    if (tid < 64) sX[tid] = xv;
   }
   __syncthreads();
 
