@@ -143,6 +143,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPEC =
   }
   __syncthreads();
 
+  // With one midpoint column per lane (TM W = 256), lane q computes the Roe
+  // state, all interpolations and the flux of midpoint column q itself, so
+  // the Roe, interpolation and flux phases need no barrier between them.
+  constexpr bool OWN = (TMW == NT);
   const bool proj = (NV > 1) && a.pp.charproj;
   if constexpr (NV > 1) {
     if (proj) {
@@ -164,7 +168,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPEC =
         r[(ND + 1) * TMW] = rs.c;
         r[(ND + 2) * TMW] = rs.ic;
       }
-      __syncthreads();
+      if constexpr (!OWN) __syncthreads();
     }
   }
 
@@ -209,7 +213,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPEC =
     }
     interp5_pair<SPEC, SPEC == SPEC_FE>(a.ip, w, sW + q, sW + NV * TMW + q, sX);
   }
-  __syncthreads();
+  if constexpr (!OWN) __syncthreads();
 
   // midpoint flux (overwrites sW rows 0..NV-1 of the same midpoint)
 #pragma unroll 1
