@@ -346,10 +346,12 @@ def main():
             "ms_per_step": round(msp, 4), "pt_stage_per_s": 3 * npl / (msp * 1e-3)}
         del plains
         # plain form on structured grids
-        for name, (pk, Uh, _) in (
-                ("plain_2d_riemann_2048", W.riemann2d(seed=args.seed, n=2048)),
-                ("plain_3d_turbulence_256", W.turbulence3d(seed=args.seed, n=256))):
-            Pg = Plan(**pk, weights=args.weights, xi=args.xi)
+        r2d = W.riemann2d(seed=args.seed, n=2048)
+        for name, (pk, Uh, _), scheme in (
+                ("plain_2d_riemann_2048", r2d, "wcns"),
+                ("plain_2d_riemann_2048_weno", r2d, "weno"),
+                ("plain_3d_turbulence_256", W.turbulence3d(seed=args.seed, n=256), "wcns")):
+            Pg = Plan(**pk, weights=args.weights, xi=args.xi, scheme=scheme)
             Ug = torch.from_numpy(Uh).to(dev)
             tiles = Pg.autotune(Ug)
             msg = time_launches(lambda: Pg.rk3_step(Ug), 3)

@@ -302,11 +302,26 @@ __device__ __forceinline__ double fe_map_frac(double w, const double (&a)[NT],
   return __builtin_fma(w, *den, num);
 }
 
+// Constants of one scheme family in the FE fast path of weigh5: the ideal
+// weights, the A_j = a_j + b_j w of its three maps, and the factor the
+// candidates passed to weigh5 are scaled by (1/8 for the WCNS candidates of
+// eq. 5, 1/6 for the WENO5 ones).
+struct FamWcns {
+  static constexpr double d0 = D0, d1 = D1, d2 = D2, scale = 0.125;
+  static constexpr const double (&m0a)[3] = kG0a;
+  static constexpr const double (&m0b)[3] = kG0b;
+  static constexpr const double (&m1a)[4] = kG1a;
+  static constexpr const double (&m1b)[4] = kG1b;
+  static constexpr const double (&m2a)[3] = kG2a;
+  static constexpr const double (&m2b)[3] = kG2b;
+};
+
 // The nonlinear weights of eq. 11 / 14 (+ FE map, eq. 20; PFE switch) from
 // the smoothness indicators, applied to the candidates of eq. 5; (c0, c1, c2)
-// are eight times the candidates (the 1/8 is applied once, to the sum).
+// are eight times the candidates (the 1/8 is applied once, to the sum).  The
+// FE branch serves either family (FAM); the generic branch is the WCNS one.
 // xt: the kExp2Tab64 table in LDS (TAB = true), else unused.
-template <int SPEC = SPEC_GENERIC, bool TAB = false>
+template <int SPEC = SPEC_GENERIC, bool TAB = false, class FAM = FamWcns>
 __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, double c1, double c2,
                                          double IS0, double IS1, double IS2,
                                          const double* xt = nullptr) {
@@ -320,19 +335,19 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     const double t2 = tau * tau;
     const double b0 = IS0 + P.eps, b1 = IS1 + P.eps, b2 = IS2 + P.eps;
     const double q0 = b0 * b0, q1 = b1 * b1, q2 = b2 * b2;
-    const double z0 = D0 * (q0 + t2) * (q1 * q2);
-    const double z1 = D1 * (q1 + t2) * (q0 * q2);
-    const double z2 = D2 * (q2 + t2) * (q0 * q1);
+    const double z0 = FAM::d0 * (q0 + t2) * (q1 * q2);
+    const double z1 = FAM::d1 * (q1 + t2) * (q0 * q2);
+    const double z2 = FAM::d2 * (q2 + t2) * (q0 * q1);
     const double zi = rcp(z0 + z1 + z2);
     const double xi2 = 2.0 * P.xi;
     // g_k = n_k / e_k; the normalised weights g_k / sum_l g_l over the
     // common denominator e_0 e_1 e_2 (below e^B, fe_map_frac): one reciprocal.
     double e0, e1, e2;
-    const double n0 = fe_map_frac<3, TAB>(z0 * zi, kG0a, kG0b, P.K, P.C2[0], xi2, xt, &e0);
-    const double n1 = fe_map_frac<4, TAB>(z1 * zi, kG1a, kG1b, P.K + 3, P.C2[1], xi2, xt, &e1);
-    const double n2 = fe_map_frac<3, TAB>(z2 * zi, kG2a, kG2b, P.K + 7, P.C2[2], xi2, xt, &e2);
+    const double n0 = fe_map_frac<3, TAB>(z0 * zi, FAM::m0a, FAM::m0b, P.K, P.C2[0], xi2, xt, &e0);
+    const double n1 = fe_map_frac<4, TAB>(z1 * zi, FAM::m1a, FAM::m1b, P.K + 3, P.C2[1], xi2, xt, &e1);
+    const double n2 = fe_map_frac<3, TAB>(z2 * zi, FAM::m2a, FAM::m2b, P.K + 7, P.C2[2], xi2, xt, &e2);
     const double T0 = n0 * (e1 * e2), T1 = n1 * (e0 * e2), T2 = n2 * (e0 * e1);
-    return (0.125 * (T0 * c0 + T1 * c1 + T2 * c2)) * rcp(T0 + T1 + T2);
+    return (FAM::scale * (T0 * c0 + T1 * c1 + T2 * c2)) * rcp(T0 + T1 + T2);
   }
   double a0, a1, a2;
   if (!FE && P.weights == WJS) {
@@ -423,6 +438,35 @@ constexpr double kV1a[4] = {0.5 * E1, 0.5 * (0.5 - E1), 0.5 * (0.75 - 0.5), -0.5
 constexpr double kV1b[4] = {-0.5, 0.0, 0.0, 0.5};
 constexpr double kV2a[3] = {0.5 * E2, 0.5 * (0.5 - E2), -0.25};
 constexpr double kV2b[3] = {-0.5, 0.0, 0.5};
+static_assert(map_sums_vanish(kV0a, kV0b, 3) && map_sums_vanish(kV1a, kV1b, 4) &&
+                  map_sums_vanish(kV2a, kV2b, 3),
+              "the WENO FE maps' A_j must sum to zero");
+
+struct FamWeno {
+  static constexpr double d0 = E0, d1 = E1, d2 = E2, scale = 1.0 / 6.0;
+  static constexpr const double (&m0a)[3] = kV0a;
+  static constexpr const double (&m0b)[3] = kV0b;
+  static constexpr const double (&m1a)[4] = kV1a;
+  static constexpr const double (&m1b)[4] = kV1b;
+  static constexpr const double (&m2a)[3] = kV2a;
+  static constexpr const double (&m2b)[3] = kV2b;
+};
+
+// weno5 with FE weights on p = 2 Z weights through the fast path of weigh5
+// (Table B.1 ideal weights, Table B.2 maps); xt: the kExp2Tab64 table in LDS.
+template <bool TAB>
+__device__ __forceinline__ double weno5_fe(const InterpParams& P, double a, double b, double c,
+                                           double e, double f, const double* xt) {
+  const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
+  const double s20 = d1 - d0, s10 = 3.0 * d1 - d0;
+  const double s21 = d2 - d1, s11 = d1 + d2;
+  const double s22 = d3 - d2, s12 = 3.0 * d2 - d3;
+  const double B0 = (13.0 / 12.0) * s20 * s20 + 0.25 * s10 * s10;
+  const double B1 = (13.0 / 12.0) * s21 * s21 + 0.25 * s11 * s11;
+  const double B2 = (13.0 / 12.0) * s22 * s22 + 0.25 * s12 * s12;
+  return weigh5<SPEC_FE, TAB, FamWeno>(P, 2.0 * a - 7.0 * b + 11.0 * c, -b + 5.0 * c + 2.0 * e,
+                                       2.0 * c + 5.0 * e - f, B0, B1, B2, xt);
+}
 
 // Finite-difference WENO5 reconstruction at x_{i+1/2} from the point values
 // (f_{i-2}, ..., f_{i+2}) = (a, b, c, e, f): Jiang-Shu smoothness indicators

@@ -15,7 +15,7 @@
 //   flux     F~ = R (f+^ + f-^) per midpoint;
 //   diff     -(F~_{i+1/2} - F~_{i-1/2}) / h, written as R, R+= or a stage.
 // LDS (doubles): sU[NV][TM+5][W] | sF[NV][TM+5][W] | sL[TM+5][W] | sR[ND+3][TMW]
-// | sA[TMW] | sW[2 NV][TMW].
+// | sA[TMW] | sW[2 NV][TMW] | the 64-entry exp table (FE specialisation).
 #include <hip/hip_runtime.h>
 
 #include "wcns_internal.hpp"
@@ -32,11 +32,11 @@ struct WenoLayout {
   static constexpr int SV = TN * W;
   static constexpr int LW = W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : 3;
   static constexpr size_t lds_doubles =
-      (size_t)(2 * NV + 1) * SV + (size_t)(NR + 1 + 2 * NV) * TMW;
+      (size_t)(2 * NV + 1) * SV + (size_t)(NR + 1 + 2 * NV) * TMW + 64;
   static_assert(TMW == 128, "WENO tiles hold 128 midpoints");
 };
 
-template <int NV, int DIR, int TM, int W>
+template <int NV, int DIR, int SPEC, int TM, int W>
 __global__ void __launch_bounds__(256) weno_sweep_kernel(SweepArgs a, TileGeom g, int mode) {
   using L = WenoLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TMW = L::TMW, SV = L::SV, LW = L::LW;
@@ -49,6 +49,7 @@ __global__ void __launch_bounds__(256) weno_sweep_kernel(SweepArgs a, TileGeom g
   double* sR = sL + SV;
   double* sA = sR + NR * TMW;
   double* sW = sA + TMW;
+  double* sX = sW + 2 * NV * TMW;  // kExp2Tab64
   const int tid = threadIdx.x;
 
   const int64_t tile = blockIdx.x;
@@ -81,6 +82,9 @@ __global__ void __launch_bounds__(256) weno_sweep_kernel(SweepArgs a, TileGeom g
   const int64_t nb = i0 - 3;  // position of LDS node 0; midpoint t is m = i0 - 1 + t
 
   // load
+  if constexpr (SPEC == SPEC_FE) {
+    if (tid < 64) sX[tid] = kExp2Tab64[tid];
+  }
   for (int idx = tid; idx < SV; idx += NT) {
     const int k = idx >> LW, c = idx & (W - 1);
     const int cc = c < ncol ? c : ncol - 1;
@@ -179,7 +183,10 @@ __global__ void __launch_bounds__(256) weno_sweep_kernel(SweepArgs a, TileGeom g
         for (int s5 = 0; s5 < 5; ++s5) w[s5] = split(v, rem + (side ? 5 - s5 : s5) * W);
       }
     }
-    sW[q] = weno5(a.ip, w[0], w[1], w[2], w[3], w[4]);
+    if constexpr (SPEC == SPEC_FE)
+      sW[q] = weno5_fe<true>(a.ip, w[0], w[1], w[2], w[3], w[4], sX);
+    else
+      sW[q] = weno5(a.ip, w[0], w[1], w[2], w[3], w[4]);
   }
   __syncthreads();
 
@@ -245,8 +252,12 @@ static hipError_t weno_go(const SweepArgs& a, int mode, hipStream_t s) {
   const int64_t others = DIR == 0 ? a.n[1] * a.n[2] : (DIR == 1 ? a.n[2] : a.n[1]);
   g.ntiles = g.segs * g.xgroups * others;
   if (g.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((weno_sweep_kernel<NV, DIR, TM, W>), dim3((unsigned)g.ntiles), dim3(256),
-                     sizeof(double) * L::lds_doubles, s, a, g, mode);
+  if (spec_of(a.ip) == SPEC_FE)
+    hipLaunchKernelGGL((weno_sweep_kernel<NV, DIR, SPEC_FE, TM, W>), dim3((unsigned)g.ntiles),
+                       dim3(256), sizeof(double) * L::lds_doubles, s, a, g, mode);
+  else
+    hipLaunchKernelGGL((weno_sweep_kernel<NV, DIR, SPEC_GENERIC, TM, W>), dim3((unsigned)g.ntiles),
+                       dim3(256), sizeof(double) * L::lds_doubles, s, a, g, mode);
   return hipGetLastError();
 }
 
