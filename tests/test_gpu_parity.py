@@ -209,19 +209,23 @@ def test_autotune_keeps_results_and_picks_a_candidate(lib, ora, W):
     _check(to_host(G.residual(Ud)), O.residual(U), what="after autotune")
 
 
+@pytest.mark.parametrize("scheme", ["wcns", "weno"])
 @pytest.mark.parametrize("xi", [10.0, 120.0, 200.0, 1000.0])
-def test_fe_residual_across_xi(lib, ora, W, xi):
+def test_fe_residual_across_xi(lib, ora, W, xi, scheme):
     """FE weights at steepnesses that select each device evaluation of the
     map: one exponential per map with unclamped products (xi = 10, 120),
     one per map with a reciprocal per term (xi = 200), one per term
-    (xi = 1000).  An evolved shock tube spreads the weights over [0, 1]."""
+    (xi = 1000), for the WCNS and the WENO (App. B) family.  An evolved
+    shock tube spreads the weights over [0, 1]."""
+    kw = dict(weights="fe", xi=xi)
+    okw = dict(kw, family=scheme)
     prob, U, _ = W.shock_tube(1.0, 0.75, 1.0, 0.125, -0.3, 0.1, 301)
-    O = ora.Problem(**prob, weights="fe", xi=xi)
+    O = ora.Problem(**prob, **okw)
     U1, bad = O.run_steps(U, 30, cfl=0.5)
     assert bad == 0
-    say("fe residual across xi", xi)
-    G = lib.Plan(**prob, weights="fe", xi=xi)
-    _check(to_host(G.residual(to_dev(U1))), O.residual(U1), what=f"fe xi={xi}")
+    say("fe residual across xi", xi, scheme)
+    G = lib.Plan(**prob, **kw, scheme=scheme)
+    _check(to_host(G.residual(to_dev(U1))), O.residual(U1), what=f"fe xi={xi} {scheme}")
     prob, U = W.random_smooth_state(4, 2, (48, 40), amp=0.3)
-    G, O = _pair(lib, ora, prob, weights="fe", xi=xi)
-    _check(to_host(G.residual(to_dev(U))), O.residual(U), what=f"fe 2d xi={xi}")
+    G, O = lib.Plan(**prob, **kw, scheme=scheme), ora.Problem(**prob, **okw)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what=f"fe 2d xi={xi} {scheme}")
