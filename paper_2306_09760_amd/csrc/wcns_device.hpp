@@ -317,23 +317,23 @@ struct FamWcns {
 };
 
 // The nonlinear weights of eq. 11 / 14 (+ FE map, eq. 20; PFE switch) from
-// the smoothness indicators, applied to the candidates of eq. 5; (c0, c1, c2)
+// the regularised smoothness indicators b_k = IS_k + eps (so that
+// tau = |IS_0 - IS_2| = |b_0 - b_2|), applied to the candidates of eq. 5; (c0, c1, c2)
 // are eight times the candidates (the 1/8 is applied once, to the sum).  The
 // FE branch serves either family (FAM); the generic branch is the WCNS one.
 // xt: the kExp2Tab64 table in LDS (TAB = true), else unused.
 template <int SPEC = SPEC_GENERIC, bool TAB = false, class FAM = FamWcns>
 __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, double c1, double c2,
-                                         double IS0, double IS1, double IS2,
+                                         double b0, double b1, double b2,
                                          const double* xt = nullptr) {
   constexpr bool FE = (SPEC == SPEC_FE);
   if constexpr (FE) {
-    // Z weights (p = 2) over the common denominator: alpha_k (IS_0 + eps)^2
-    // (IS_1 + eps)^2 (IS_2 + eps)^2 = d_k ((IS_k + eps)^2 + tau^2) times the
-    // other two squares; one reciprocal normalises them.  The smallest
-    // product, eps^6 = 1e-240, is still a normal number.
-    const double tau = __builtin_fabs(IS0 - IS2);
+    // Z weights (p = 2) over the common denominator: alpha_k b_0^2 b_1^2 b_2^2
+    // = d_k (b_k^2 + tau^2) times the other two squares; one reciprocal
+    // normalises them.  The smallest product, eps^6 = 1e-240, is still a
+    // normal number.
+    const double tau = __builtin_fabs(b0 - b2);
     const double t2 = tau * tau;
-    const double b0 = IS0 + P.eps, b1 = IS1 + P.eps, b2 = IS2 + P.eps;
     const double q0 = b0 * b0, q1 = b1 * b1, q2 = b2 * b2;
     const double z0 = FAM::d0 * (q0 + t2) * (q1 * q2);
     const double z1 = FAM::d1 * (q1 + t2) * (q0 * q2);
@@ -346,18 +346,20 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     const double n0 = fe_map_frac<3, TAB>(z0 * zi, FAM::m0a, FAM::m0b, P.K, P.C2[0], xi2, xt, &e0);
     const double n1 = fe_map_frac<4, TAB>(z1 * zi, FAM::m1a, FAM::m1b, P.K + 3, P.C2[1], xi2, xt, &e1);
     const double n2 = fe_map_frac<3, TAB>(z2 * zi, FAM::m2a, FAM::m2b, P.K + 7, P.C2[2], xi2, xt, &e2);
-    const double T0 = n0 * (e1 * e2), T1 = n1 * (e0 * e2), T2 = n2 * (e0 * e1);
-    return (FAM::scale * (T0 * c0 + T1 * c1 + T2 * c2)) * rcp(T0 + T1 + T2);
+    // T_k = n_k prod_{l != k} e_l: T_0 = A e_2, T_1 = B e_2, T_2 = C
+    const double A = n0 * e1, B = n1 * e0, C = n2 * (e0 * e1);
+    const double num = __builtin_fma(e2, __builtin_fma(A, c0, B * c1), C * c2);
+    return (FAM::scale * num) * rcp(__builtin_fma(e2, A + B, C));
   }
   double a0, a1, a2;
   if (!FE && P.weights == WJS) {
-    const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
+    const double r0 = rcp(b0), r1 = rcp(b1), r2 = rcp(b2);
     a0 = D0 * r0 * r0;
     a1 = D1 * r1 * r1;
     a2 = D2 * r2 * r2;
   } else {
-    const double tau = __builtin_fabs(IS0 - IS2);
-    double q0 = tau * rcp(IS0 + P.eps), q1 = tau * rcp(IS1 + P.eps), q2 = tau * rcp(IS2 + P.eps);
+    const double tau = __builtin_fabs(b0 - b2);
+    double q0 = tau * rcp(b0), q1 = tau * rcp(b1), q2 = tau * rcp(b2);
     double p0 = q0, p1 = q1, p2 = q2;
     const int zpow = FE ? 2 : P.zpow;
     for (int k = 1; k < zpow; ++k) {
@@ -419,12 +421,13 @@ __device__ __forceinline__ void interp5_pair(const InterpParams& P, const double
   const double d0 = u[1] - u[0], d1 = u[2] - u[1], d2 = u[3] - u[2], d3 = u[4] - u[3],
                d4 = u[5] - u[4];
   const double s0 = d1 - d0, s1 = d2 - d1, s2 = d3 - d2, s3 = d4 - d3;
-  const double q1 = s1 * s1, q2 = s2 * s2;
+  // IS_k + eps = f_k^2 + (s_k^2 + eps)
+  const double q1 = __builtin_fma(s1, s1, P.eps), q2 = __builtin_fma(s2, s2, P.eps);
   const double f0 = 0.5 * (3.0 * d1 - d0), f1 = 0.5 * (d1 + d2), f2 = 0.5 * (3.0 * d2 - d3);
   const double g0 = 0.5 * (3.0 * d3 - d4), g1 = 0.5 * (d2 + d3), g2 = 0.5 * (3.0 * d2 - d1);
-  *left = weigh5<SPEC, TAB>(P, c0, c1, c2, __builtin_fma(s0, s0, f0 * f0),
+  *left = weigh5<SPEC, TAB>(P, c0, c1, c2, __builtin_fma(f0, f0, __builtin_fma(s0, s0, P.eps)),
                             __builtin_fma(f1, f1, q1), __builtin_fma(f2, f2, q2), xt);
-  *right = weigh5<SPEC, TAB>(P, r0, r1, r2, __builtin_fma(s3, s3, g0 * g0),
+  *right = weigh5<SPEC, TAB>(P, r0, r1, r2, __builtin_fma(g0, g0, __builtin_fma(s3, s3, P.eps)),
                              __builtin_fma(g1, g1, q2), __builtin_fma(g2, g2, q1), xt);
 }
 
@@ -465,7 +468,8 @@ __device__ __forceinline__ double weno5_fe(const InterpParams& P, double a, doub
   const double B1 = (13.0 / 12.0) * s21 * s21 + 0.25 * s11 * s11;
   const double B2 = (13.0 / 12.0) * s22 * s22 + 0.25 * s12 * s12;
   return weigh5<SPEC_FE, TAB, FamWeno>(P, 2.0 * a - 7.0 * b + 11.0 * c, -b + 5.0 * c + 2.0 * e,
-                                       2.0 * c + 5.0 * e - f, B0, B1, B2, xt);
+                                       2.0 * c + 5.0 * e - f, B0 + P.eps, B1 + P.eps,
+                                       B2 + P.eps, xt);
 }
 
 // Finite-difference WENO5 reconstruction at x_{i+1/2} from the point values
