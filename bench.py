@@ -270,17 +270,30 @@ def main():
         a1.record()
         torch.cuda.synchronize()
         adj_ms = a0.elapsed_time(a1) / reps
+        # the same step reversed from stored stage states (no recomputation)
+        S1, S2 = torch.empty_like(U5d), torch.empty_like(U5d)
+        Us = U5d.clone()
+        P5.rk3_step_stages(Us, S1, S2, dt=dt5)
+        P5.rk3_step_adjoint(U5d, lam, dt5, stages=(S1, S2))
+        torch.cuda.synchronize()
+        a0.record()
+        for _ in range(reps):
+            P5.rk3_step_adjoint(U5d, lam, dt5, stages=(S1, S2))
+        a1.record()
+        torch.cuda.synchronize()
+        adj_st_ms = a0.elapsed_time(a1) / reps
+        del S1, S2, Us
 
         # 100-step differentiable rollout of J = 1/2 ||rho(T)||^2-type loss:
         # forward, then backward with every state stored (no recompute) and
         # with 9 checkpoints besides U0 (binomial recompute)
         nsteps = 100
 
-        def roll(snap):
+        def roll(snap, stages=False):
             X = U5d.clone().requires_grad_(True)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            UT = RO.rollout(P5, X, dt5, nsteps, snap)
+            UT = RO.rollout(P5, X, dt5, nsteps, snap, stages=stages)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             UT[0].sum().backward()
@@ -291,17 +304,24 @@ def main():
         roll(nsteps - 1)  # warm
         f_all, b_all = roll(nsteps - 1)
         f_rev, b_rev = roll(9)
+        f_st, b_st = roll(0, stages=True)
         adjoint = {"workload": "2D Euler periodic 1024^2, smooth rho, u, v, p, FE xi=%g" % args.xi,
                    "forward_step_ms": round(fwd_ms, 4), "adjoint_step_ms": round(adj_ms, 4),
                    "ratio": round(adj_ms / fwd_ms, 3),
+                   "adjoint_step_ms_stages_stored": round(adj_st_ms, 4),
+                   "ratio_stages_stored": round(adj_st_ms / fwd_ms, 3),
                    "rollout_steps": nsteps,
                    "rollout_forward_ms": round(f_all, 2),
                    "rollout_backward_ms_all_states_stored": round(b_all, 2),
                    "rollout_backward_ms_9_checkpoints": round(b_rev, 2),
                    "recomputed_steps_9_checkpoints": RO.schedule_cost(nsteps, 9),
+                   "rollout_forward_ms_stages_stored": round(f_st, 2),
+                   "rollout_backward_ms_stages_stored": round(b_st, 2),
                    "ratio_rollout_no_recompute": round(b_all / f_all, 3),
                    "ratio_rollout_with_recompute": round(b_rev / f_rev, 3),
-                   "note": "adjoint step recomputes its two stage states"}
+                   "ratio_rollout_stages_stored": round(b_st / f_all, 3),
+                   "note": "adjoint_step_ms recomputes the step's two stage states; "
+                           "*_stages_stored reverses from the stage states the forward kept"}
 
     # ---- other forms on the same GPU --------------------------------------
     forms = None

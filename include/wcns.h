@@ -132,6 +132,16 @@ wcns_status wcns_cfl_dt(wcns_plan* plan, const double* U, double cfl, double* dt
 wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev,
                           double cfl, int32_t* status_dev, void* stream);
 
+/* wcns_rk3_step that also leaves its stage states: U1 <- U^(1) = U^n + dt
+   L(U^n), U2 <- U^(2) = 3/4 U^n + 1/4 (U^(1) + dt L(U^(1))), then U <-
+   U^{n+1}.  U1, U2: device arrays of wcns_state_elems doubles owned by the
+   caller, distinct from U and from each other (WCNS_EINVAL otherwise); kept
+   for wcns_rk3_step_adjoint_stages, which then needs no recomputation.  The
+   step itself is identical to wcns_rk3_step.  Graph-capturable. */
+wcns_status wcns_rk3_step_stages(wcns_plan* plan, double* U, double* U1, double* U2, void* work,
+                                 const double* dt_dev, double cfl, int32_t* status_dev,
+                                 void* stream);
+
 /* One step in place of the four-stage Runge-Kutta scheme of eq. 16 (the
    paper's integrator, classical RK4): u1 = u + dt/2 L(u), u2 = u + dt/2
    L(u1), u3 = u + dt L(u2), u <- -u/3 + u1/3 + 2 u2/3 + u3/3 + dt/6 L(u3).
@@ -167,6 +177,14 @@ wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double
    adjoint of U^n.  Uses `work`. */
 wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lambda,
                                   void* work, const double* dt_dev, void* stream);
+
+/* wcns_rk3_step_adjoint from the stage states U1, U2 that
+   wcns_rk3_step_stages wrote for the step from Un with the same *dt_dev:
+   the same reverse sweep without recomputing the two stage states (two
+   residual evaluations fewer).  Uses `work`. */
+wcns_status wcns_rk3_step_adjoint_stages(wcns_plan* plan, const double* Un, const double* U1,
+                                         const double* U2, double* lambda, void* work,
+                                         const double* dt_dev, void* stream);
 
 /* Measures the candidate tile shapes of this plan's kernels on U (timed with
    HIP events; synchronises the stream) and keeps the fastest in the plan and

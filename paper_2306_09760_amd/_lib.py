@@ -25,9 +25,11 @@ SCHEMES = {"wcns": 0, "weno": 1}
 # Every entry point declared in include/wcns.h.
 EXPORTS = [
     "wcns_desc_init", "wcns_plan_create", "wcns_plan_destroy", "wcns_state_elems",
-    "wcns_workspace_bytes", "wcns_residual", "wcns_cfl_dt", "wcns_rk3_step", "wcns_rk4_step",
+    "wcns_workspace_bytes", "wcns_residual", "wcns_cfl_dt", "wcns_rk3_step",
+    "wcns_rk3_step_stages", "wcns_rk4_step",
     "wcns_weight_histogram",
-    "wcns_residual_adjoint", "wcns_rk3_step_adjoint", "wcns_plan_autotune",
+    "wcns_residual_adjoint", "wcns_rk3_step_adjoint", "wcns_rk3_step_adjoint_stages",
+    "wcns_plan_autotune",
     "wcns_plan_get_tiles", "wcns_plan_set_tiles", "wcns_batch_plan_create",
     "wcns_batch_plan_destroy", "wcns_batch_state_elems", "wcns_batch_workspace_bytes",
     "wcns_batch_residual", "wcns_batch_rk3_step", "wcns_batch_set_graph",
@@ -75,10 +77,12 @@ def lib():
         "wcns_residual": (st, [vp, vp, vp, vp, vp]),
         "wcns_cfl_dt": (st, [vp, vp, C.c_double, vp, vp, vp]),
         "wcns_rk3_step": (st, [vp, vp, vp, vp, C.c_double, vp, vp]),
+        "wcns_rk3_step_stages": (st, [vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]),
         "wcns_rk4_step": (st, [vp, vp, vp, vp, C.c_double, vp, vp]),
         "wcns_weight_histogram": (st, [vp, vp, vp, C.c_int32, vp]),
         "wcns_residual_adjoint": (st, [vp, vp, vp, vp, vp, vp]),
         "wcns_rk3_step_adjoint": (st, [vp, vp, vp, vp, vp, vp]),
+        "wcns_rk3_step_adjoint_stages": (st, [vp, vp, vp, vp, vp, vp, vp, vp]),
         "wcns_plan_autotune": (st, [vp, vp, vp, vp]),
         "wcns_plan_get_tiles": (None, [vp, ip]),
         "wcns_plan_set_tiles": (st, [vp, ip]),

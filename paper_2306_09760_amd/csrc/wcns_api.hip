@@ -432,14 +432,12 @@ wcns_status wcns_cfl_dt(wcns_plan* plan, const double* U, double cfl, double* dt
   return WCNS_OK;
 }
 
-wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev, double cfl,
-                          int32_t* status_dev, void* stream) {
-  g_err.clear();
-  if (!plan || !U || !work) return fail(WCNS_EINVAL, "NULL argument");
+namespace {
+// One SSP-RK3 step of U in place with the stage states in W1, W2.
+wcns_status rk3_step_into(wcns_plan* plan, double* U, double* W1, double* W2, void* work,
+                          const double* dt_dev, double cfl, int32_t* status_dev, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)work;
-  double* W1 = (double*)(w + plan->off_W1);
-  double* W2 = (double*)(w + plan->off_W2);
   double* Racc = (double*)(w + plan->off_R);
   const double* dt = dt_dev;
   if (!dt) {
@@ -455,6 +453,25 @@ wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* 
   if ((st = stage(plan, W1, U, W2, 0.75, 0.25, dt, Racc, status_dev, s)) != WCNS_OK) return st;
   if ((st = stage(plan, W2, U, U, 1.0 / 3.0, 2.0 / 3.0, dt, Racc, status_dev, s)) != WCNS_OK) return st;
   return WCNS_OK;
+}
+}  // namespace
+
+wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev, double cfl,
+                          int32_t* status_dev, void* stream) {
+  g_err.clear();
+  if (!plan || !U || !work) return fail(WCNS_EINVAL, "NULL argument");
+  char* w = (char*)work;
+  return rk3_step_into(plan, U, (double*)(w + plan->off_W1), (double*)(w + plan->off_W2), work,
+                       dt_dev, cfl, status_dev, stream);
+}
+
+wcns_status wcns_rk3_step_stages(wcns_plan* plan, double* U, double* U1, double* U2, void* work,
+                                 const double* dt_dev, double cfl, int32_t* status_dev,
+                                 void* stream) {
+  g_err.clear();
+  if (!plan || !U || !U1 || !U2 || !work) return fail(WCNS_EINVAL, "NULL argument");
+  if (U1 == U || U2 == U || U1 == U2) return fail(WCNS_EINVAL, "U, U1 and U2 must be distinct");
+  return rk3_step_into(plan, U, U1, U2, work, dt_dev, cfl, status_dev, stream);
 }
 
 wcns_status wcns_rk4_step(wcns_plan* plan, double* U, void* work, const double* dt_dev, double cfl,
@@ -535,28 +552,18 @@ wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double
   return WCNS_OK;
 }
 
-wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lambda, void* work,
-                                  const double* dt_dev, void* stream) {
-  g_err.clear();
-  if (!plan || !Un || !lambda || !work || !dt_dev) return fail(WCNS_EINVAL, "NULL argument");
-  if (plan->d.scheme != WCNS_SCHEME_WCNS)
-    return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
+namespace {
+// Reverse of one SSP-RK3 step given its stage states U1, U2.
+wcns_status rk3_adjoint_from_stages(wcns_plan* plan, const double* Un, const double* U1,
+                                    const double* U2, double* lambda, void* work,
+                                    const double* dt_dev, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)work;
   const int64_t len = plan->nv * plan->npts;
-  double* U1 = (double*)(w + plan->off_W1);
-  double* U2 = (double*)(w + plan->off_W2);
-  double* L = (double*)(w + plan->off_R);
   double* l2 = (double*)(w + plan->off_A1);
   double* l1 = (double*)(w + plan->off_A2);
   double* tmp = (double*)(w + plan->off_A3);
   wcns_status st;
-  // Recompute the stage states U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 (U1 + dt L(U1)).
-  if ((st = residual_into(plan, Un, L, s)) != WCNS_OK) return st;
-  WCNS_HIP(launch_lincomb(U1, Un, 1.0, L, 0.0, dt_dev, 1.0, len, s), "lincomb");
-  if ((st = residual_into(plan, U1, L, s)) != WCNS_OK) return st;
-  WCNS_HIP(launch_lincomb(U2, U1, 0.25, L, 0.0, dt_dev, 0.25, len, s), "lincomb");
-  WCNS_HIP(launch_axpy_state(U2, Un, 0.75, len, s), "axpy");
   // Stage 3: U3 = 1/3 Un + 2/3 U2 + 2/3 dt L(U2), lambda = adjoint of U3.
   //   l2 = 2/3 lambda + 2/3 dt J(U2)^T lambda
   WCNS_HIP(launch_zero(tmp, len, s), "zero");
@@ -576,6 +583,40 @@ wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lam
   WCNS_HIP(launch_axpy_state(lambda, l1, 1.0, len, s), "axpy");
   WCNS_HIP(launch_lincomb(lambda, lambda, 1.0, tmp, 0.0, dt_dev, 1.0, len, s), "lincomb");
   return WCNS_OK;
+}
+}  // namespace
+
+wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lambda, void* work,
+                                  const double* dt_dev, void* stream) {
+  g_err.clear();
+  if (!plan || !Un || !lambda || !work || !dt_dev) return fail(WCNS_EINVAL, "NULL argument");
+  if (plan->d.scheme != WCNS_SCHEME_WCNS)
+    return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)work;
+  const int64_t len = plan->nv * plan->npts;
+  double* U1 = (double*)(w + plan->off_W1);
+  double* U2 = (double*)(w + plan->off_W2);
+  double* L = (double*)(w + plan->off_R);
+  wcns_status st;
+  // Recompute the stage states U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 (U1 + dt L(U1)).
+  if ((st = residual_into(plan, Un, L, s)) != WCNS_OK) return st;
+  WCNS_HIP(launch_lincomb(U1, Un, 1.0, L, 0.0, dt_dev, 1.0, len, s), "lincomb");
+  if ((st = residual_into(plan, U1, L, s)) != WCNS_OK) return st;
+  WCNS_HIP(launch_lincomb(U2, U1, 0.25, L, 0.0, dt_dev, 0.25, len, s), "lincomb");
+  WCNS_HIP(launch_axpy_state(U2, Un, 0.75, len, s), "axpy");
+  return rk3_adjoint_from_stages(plan, Un, U1, U2, lambda, work, dt_dev, stream);
+}
+
+wcns_status wcns_rk3_step_adjoint_stages(wcns_plan* plan, const double* Un, const double* U1,
+                                         const double* U2, double* lambda, void* work,
+                                         const double* dt_dev, void* stream) {
+  g_err.clear();
+  if (!plan || !Un || !U1 || !U2 || !lambda || !work || !dt_dev)
+    return fail(WCNS_EINVAL, "NULL argument");
+  if (plan->d.scheme != WCNS_SCHEME_WCNS)
+    return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
+  return rk3_adjoint_from_stages(plan, Un, U1, U2, lambda, work, dt_dev, stream);
 }
 
 wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, void* stream) {

@@ -23,6 +23,12 @@ checkpoint fewer, release it, then reverse the first j steps.  The first
 chain of "advance and keep" moves is exactly the forward pass, so the
 forward pass stores those states and the backward pass starts from them.
 
+With ``stages=True`` the forward pass keeps every step's start state and
+both stage states (``wcns_rk3_step_stages``, three states per step) and the
+backward pass reverses each step from them (``wcns_rk3_step_adjoint_stages``)
+without any recomputation: memory traded for the two residual evaluations
+per step that the adjoint step otherwise repeats.
+
 dt is held fixed (a CFL-limited dt depends on the state, and its derivative
 is not part of the step adjoint).  Every step runs on the GPU; this module
 only orders the calls.
@@ -87,6 +93,28 @@ def checkpoint_positions(nsteps: int, snapshots: int):
     return pos
 
 
+class _StagedRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, U0, plan, dt, nsteps):
+        U = U0.detach().clone()
+        saved = []
+        for _ in range(nsteps):
+            Un = U.clone()
+            U1, U2 = torch.empty_like(U), torch.empty_like(U)
+            plan.rk3_step_stages(U, U1, U2, dt=dt)
+            saved.append((Un, U1, U2))
+        ctx.plan, ctx.dt, ctx.saved = plan, dt, saved
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        lam = gU.detach().clone().contiguous()
+        for Un, U1, U2 in reversed(ctx.saved):
+            ctx.plan.rk3_step_adjoint(Un, lam, ctx.dt, stages=(U1, U2))
+        ctx.saved = None
+        return lam, None, None, None
+
+
 class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, U0, plan, dt, nsteps, snapshots):
@@ -140,11 +168,16 @@ class _Rollout(torch.autograd.Function):
         return lam, None, None, None, None
 
 
-def rollout(plan, U0: torch.Tensor, dt: torch.Tensor, nsteps: int, snapshots: int = 8):
+def rollout(plan, U0: torch.Tensor, dt: torch.Tensor, nsteps: int, snapshots: int = 8,
+            stages: bool = False):
     """U(T) after ``nsteps`` SSP-RK3 steps of size ``dt`` (a (1,) device
     tensor); differentiable with respect to ``U0``.  ``snapshots`` bounds
     the number of stored states besides ``U0``; snapshots >= nsteps - 1
-    stores every state and recomputes nothing."""
+    stores every state, and the backward pass then recomputes no step but
+    still each step's two stage states.  ``stages=True`` stores those too
+    (3 nsteps states; ``snapshots`` is then ignored)."""
     if nsteps < 0:
         raise ValueError("nsteps must be >= 0")
+    if stages:
+        return _StagedRollout.apply(U0, plan, dt, int(nsteps))
     return _Rollout.apply(U0, plan, dt, int(nsteps), int(snapshots))

@@ -88,6 +88,15 @@ class Plan:
                                   _ptr(status), _stream()), "wcns_rk3_step")
         return U
 
+    def rk3_step_stages(self, U, U1, U2, dt=None, cfl=0.5, status=None):
+        """rk3_step that also writes the stage states U^(1), U^(2) to U1, U2."""
+        for X in (U, U1, U2):
+            self._check_state(X)
+        check(lib().wcns_rk3_step_stages(self._h, _ptr(U), _ptr(U1), _ptr(U2), _ptr(self.work),
+                                         _ptr(dt), cfl, _ptr(status), _stream()),
+              "wcns_rk3_step_stages")
+        return U
+
     def rk4_step(self, U, dt=None, cfl=0.3, status=None):
         """In-place step of the four-stage scheme of eq. 16; dt as rk3_step."""
         self._check_state(U)
@@ -142,11 +151,22 @@ class Plan:
                                           _ptr(self.work), _stream()), "wcns_residual_adjoint")
         return Ubar
 
-    def rk3_step_adjoint(self, Un, lam, dt):
+    def rk3_step_adjoint(self, Un, lam, dt, stages=None):
+        """lam <- adjoint of U^n from the adjoint of U^{n+1} (step of size
+        dt from Un); stages = (U1, U2) from rk3_step_stages skips their
+        recomputation."""
         self._check_state(Un)
         self._check_state(lam)
-        check(lib().wcns_rk3_step_adjoint(self._h, _ptr(Un), _ptr(lam), _ptr(self.work),
-                                          _ptr(dt), _stream()), "wcns_rk3_step_adjoint")
+        if stages is None:
+            check(lib().wcns_rk3_step_adjoint(self._h, _ptr(Un), _ptr(lam), _ptr(self.work),
+                                              _ptr(dt), _stream()), "wcns_rk3_step_adjoint")
+        else:
+            U1, U2 = stages
+            self._check_state(U1)
+            self._check_state(U2)
+            check(lib().wcns_rk3_step_adjoint_stages(self._h, _ptr(Un), _ptr(U1), _ptr(U2),
+                                                     _ptr(lam), _ptr(self.work), _ptr(dt),
+                                                     _stream()), "wcns_rk3_step_adjoint_stages")
         return lam
 
     def autotune(self, U):

@@ -98,6 +98,42 @@ def test_rk3_step_adjoint_dot_product(lib, ora, W):
     assert abs(lhs - rhs) <= 1e-10 * abs(rhs) + 1e-12
 
 
+def test_rk3_step_stages_and_adjoint_from_stages(lib, ora, W):
+    """wcns_rk3_step_stages takes the same step as wcns_rk3_step and leaves
+    U^(1) = U + dt L(U), U^(2) = 3/4 U + 1/4 (U^(1) + dt L(U^(1))); the
+    adjoint from those stages passes the oracle's dot-product test and agrees
+    with the recomputing adjoint."""
+    prob, U = W.random_smooth_state(24, 2, (16, 14), amp=0.25)
+    say("rk3 step stages")
+    G = lib.Plan(**prob, weights="fe", xi=100.0)
+    O = ora.Problem(**prob, weights="fe", xi=100.0)
+    dt = 0.2 * O.cfl_dt(U, 0.5)
+    dtd = torch.full((1,), dt, dtype=torch.float64, device="cuda")
+    Ua, Ub = to_dev(U), to_dev(U)
+    U1, U2 = torch.empty_like(Ua), torch.empty_like(Ua)
+    G.rk3_step(Ua, dt=dtd)
+    G.rk3_step_stages(Ub, U1, U2, dt=dtd)
+    assert torch.equal(Ua, Ub)
+    R0 = to_host(G.residual(to_dev(U)))
+    e1 = U + dt * R0
+    assert np.linalg.norm(to_host(U1) - e1) <= 1e-14 * np.linalg.norm(e1)
+    R1 = to_host(G.residual(U1))
+    e2 = 0.75 * U + 0.25 * (to_host(U1) + dt * R1)
+    assert np.linalg.norm(to_host(U2) - e2) <= 1e-14 * np.linalg.norm(e2)
+    rng = np.random.default_rng(5)
+    V = rng.standard_normal(U.shape)
+    lam = rng.standard_normal(U.shape)
+    _, JV, _ = O.rk3_step_jvp(U, V, dt)
+    la, lb = to_dev(lam), to_dev(lam)
+    G.rk3_step_adjoint(to_dev(U), la, dtd)
+    G.rk3_step_adjoint(to_dev(U), lb, dtd, stages=(U1, U2))
+    la, lb = to_host(la), to_host(lb)
+    assert np.linalg.norm(lb - la) <= 1e-12 * np.linalg.norm(la)
+    lhs = float(np.sum(lb * V))
+    rhs = float(np.sum(lam * JV))
+    assert abs(lhs - rhs) <= 1e-10 * abs(rhs) + 1e-12
+
+
 def test_adjoint_matches_central_differences_of_gpu_forward(lib, W):
     prob, U = W.random_smooth_state(25, 2, (24, 20), amp=0.25)
     say("adjoint vs fd")
