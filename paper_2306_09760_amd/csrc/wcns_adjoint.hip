@@ -400,8 +400,19 @@ __global__ void __launch_bounds__(256)
       node_flux_vjp<NV, DIR>(a.pp, U, Fb, acc);
     }
     const int64_t gidx = base + i * stride + c;
+    const double sc = a.dt ? a.scale * *a.dt : a.scale;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a.Ubar[v * a.npts + gidx] += a.scale * acc[v];
+    for (int v = 0; v < NV; ++v) {
+      const int64_t e = v * a.npts + gidx;
+      double y;
+      if (a.A) {
+        y = a.ca * a.A[e];
+        if (a.B) y = __builtin_fma(a.cb, a.B[e], y);
+      } else {
+        y = a.Ubar[e];
+      }
+      a.Ubar[e] = __builtin_fma(sc, acc[v], y);
+    }
   }
 }
 

@@ -193,7 +193,7 @@ struct wcns_plan {
   InterpParams ip;
   double ih[3];
   int ncfl;
-  size_t off_W1, off_W2, off_R, off_partial, off_dt, off_A1, off_A2, off_A3, bytes;
+  size_t off_W1, off_W2, off_R, off_partial, off_dt, off_A1, off_A2, bytes;
 };
 
 struct wcns_batch_plan {
@@ -372,7 +372,6 @@ wcns_status wcns_plan_create(const wcns_desc* desc, wcns_plan** plan) {
   P->off_R = o; o += align256(state);
   P->off_A1 = o; o += align256(state);
   P->off_A2 = o; o += align256(state);
-  P->off_A3 = o; o += align256(state);
   P->off_partial = o; o += align256(sizeof(double) * P->ncfl);
   P->off_dt = o; o += 256;
   P->bytes = o;
@@ -524,20 +523,27 @@ wcns_status wcns_weight_histogram(wcns_plan* plan, const double* U, uint64_t* hi
   return WCNS_OK;
 }
 
-wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double* Rbar,
-                                  double* Ubar, void* work, void* stream) {
-  g_err.clear();
-  if (!plan || !U || !Rbar || !Ubar || !work) return fail(WCNS_EINVAL, "NULL argument");
-  if (Ubar == U || Ubar == Rbar) return fail(WCNS_EINVAL, "Ubar must not alias U or Rbar");
-  if (plan->d.scheme != WCNS_SCHEME_WCNS)
-    return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
+namespace {
+// Ubar = ca A + cb B + scale dt (dL/dU)^T Rbar (A set; the first direction
+// writes, the others accumulate) or Ubar += scale dt (dL/dU)^T Rbar (A null);
+// dt_dev may be null (factor 1).
+wcns_status adjoint_into(wcns_plan* plan, const double* U, const double* Rbar, double* Ubar,
+                         double scale, const double* dt_dev, const double* A, double ca,
+                         const double* B, double cb, void* stream) {
   for (int d = 0; d < plan->d.ndim; ++d) {
     AdjArgs a;
     std::memset(&a, 0, sizeof a);
     a.U = U;
     a.Rbar = Rbar;
     a.Ubar = Ubar;
-    a.scale = 1.0;
+    a.scale = scale;
+    a.dt = dt_dev;
+    if (d == 0) {
+      a.A = A;
+      a.ca = ca;
+      a.B = B;
+      a.cb = cb;
+    }
     a.npts = plan->npts;
     for (int k = 0; k < 3; ++k) a.n[k] = plan->d.n[k];
     a.bc = plan->d.bc[d];
@@ -551,6 +557,17 @@ wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double
   }
   return WCNS_OK;
 }
+}  // namespace
+
+wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double* Rbar,
+                                  double* Ubar, void* work, void* stream) {
+  g_err.clear();
+  if (!plan || !U || !Rbar || !Ubar || !work) return fail(WCNS_EINVAL, "NULL argument");
+  if (Ubar == U || Ubar == Rbar) return fail(WCNS_EINVAL, "Ubar must not alias U or Rbar");
+  if (plan->d.scheme != WCNS_SCHEME_WCNS)
+    return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
+  return adjoint_into(plan, U, Rbar, Ubar, 1.0, nullptr, nullptr, 0.0, nullptr, 0.0, stream);
+}
 
 namespace {
 // Reverse of one SSP-RK3 step given its stage states U1, U2.
@@ -562,27 +579,21 @@ wcns_status rk3_adjoint_from_stages(wcns_plan* plan, const double* Un, const dou
   const int64_t len = plan->nv * plan->npts;
   double* l2 = (double*)(w + plan->off_A1);
   double* l1 = (double*)(w + plan->off_A2);
-  double* tmp = (double*)(w + plan->off_A3);
   wcns_status st;
-  // Stage 3: U3 = 1/3 Un + 2/3 U2 + 2/3 dt L(U2), lambda = adjoint of U3.
+  // Stage 3: U3 = 1/3 Un + 2/3 U2 + 2/3 dt L(U2), lambda = adjoint of U3:
   //   l2 = 2/3 lambda + 2/3 dt J(U2)^T lambda
-  WCNS_HIP(launch_zero(tmp, len, s), "zero");
-  if ((st = wcns_residual_adjoint(plan, U2, lambda, tmp, work, stream)) != WCNS_OK) return st;
-  WCNS_HIP(launch_lincomb(l2, lambda, 2.0 / 3.0, tmp, 0.0, dt_dev, 2.0 / 3.0, len, s), "lincomb");
-  //   lambda_n = 1/3 lambda (accumulated in place below)
-  WCNS_HIP(launch_lincomb(lambda, lambda, 1.0 / 3.0, tmp, 0.0, nullptr, 0.0, len, s), "lincomb");
-  // Stage 2: U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1).
-  //   l1 = 1/4 l2 + 1/4 dt J(U1)^T l2 ; lambda_n += 3/4 l2
-  WCNS_HIP(launch_zero(tmp, len, s), "zero");
-  if ((st = wcns_residual_adjoint(plan, U1, l2, tmp, work, stream)) != WCNS_OK) return st;
-  WCNS_HIP(launch_lincomb(l1, l2, 0.25, tmp, 0.0, dt_dev, 0.25, len, s), "lincomb");
-  WCNS_HIP(launch_axpy_state(lambda, l2, 0.75, len, s), "axpy");
-  // Stage 1: U1 = Un + dt L(Un).  lambda_n += l1 + dt J(Un)^T l1
-  WCNS_HIP(launch_zero(tmp, len, s), "zero");
-  if ((st = wcns_residual_adjoint(plan, Un, l1, tmp, work, stream)) != WCNS_OK) return st;
-  WCNS_HIP(launch_axpy_state(lambda, l1, 1.0, len, s), "axpy");
-  WCNS_HIP(launch_lincomb(lambda, lambda, 1.0, tmp, 0.0, dt_dev, 1.0, len, s), "lincomb");
-  return WCNS_OK;
+  if ((st = adjoint_into(plan, U2, lambda, l2, 2.0 / 3.0, dt_dev, lambda, 2.0 / 3.0, nullptr, 0.0,
+                         stream)) != WCNS_OK)
+    return st;
+  // Stage 2: U2 = 3/4 Un + 1/4 U1 + 1/4 dt L(U1):
+  //   l1 = 1/4 l2 + 1/4 dt J(U1)^T l2
+  if ((st = adjoint_into(plan, U1, l2, l1, 0.25, dt_dev, l2, 0.25, nullptr, 0.0, stream)) !=
+      WCNS_OK)
+    return st;
+  //   lambda_n so far: 1/3 lambda (stage 3) + 3/4 l2 (stage 2)
+  WCNS_HIP(launch_lincomb(lambda, lambda, 1.0 / 3.0, l2, 0.75, nullptr, 0.0, len, s), "lincomb");
+  // Stage 1: U1 = Un + dt L(Un):  lambda_n += l1 + dt J(Un)^T l1
+  return adjoint_into(plan, Un, l1, lambda, 1.0, dt_dev, lambda, 1.0, l1, 1.0, stream);
 }
 }  // namespace
 

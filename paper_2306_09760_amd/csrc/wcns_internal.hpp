@@ -74,7 +74,6 @@ hipError_t launch_axpy_state(double* y, const double* x, double a, int64_t n,
                              hipStream_t stream);
 hipError_t launch_lincomb(double* out, const double* x, double ax, const double* y, double ay,
                           const double* dt, double ydt, int64_t n, hipStream_t stream);
-hipError_t launch_zero(double* y, int64_t n, hipStream_t stream);
 // The filtered embedded WENO sweep of App. B (wcns_weno.hip).
 hipError_t launch_weno_sweep(int nv, int dir, const SweepArgs& a, int mode, hipStream_t stream);
 // Weight histograms of one direction's interpolations (wcns_stats.hip).
@@ -85,8 +84,15 @@ hipError_t launch_weight_hist(int nv, int dir, const SweepArgs& a, unsigned long
 struct AdjArgs {
   const double* U;      // state
   const double* Rbar;   // cotangent of the residual
-  double* Ubar;         // accumulated cotangent of U
-  double scale;         // Ubar += scale * (dL/dU)^T Rbar
+  double* Ubar;         // cotangent of U (output)
+  // Ubar = ca A + cb B + s (dL/dU)^T Rbar when A is set (B optional; A or B
+  // may be Ubar itself), else Ubar += s (dL/dU)^T Rbar; s = scale * (*dt)
+  // when dt is set, else scale
+  double scale;
+  const double* dt;
+  const double* A;
+  const double* B;
+  double ca, cb;
   int64_t npts;
   int64_t n[3];
   int32_t bc;

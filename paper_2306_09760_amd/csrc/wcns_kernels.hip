@@ -120,12 +120,6 @@ __global__ void lincomb_kernel(double* __restrict__ out, const double* __restric
   }
 }
 
-__global__ void zero_kernel(double* __restrict__ y, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = 0.0;
-}
-
 // --------------------------------------------------------------- launchers --
 static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -193,11 +187,6 @@ hipError_t launch_lincomb(double* out, const double* x, double ax, const double*
 hipError_t launch_axpy_state(double* y, const double* x, double a, int64_t n,
                              hipStream_t stream) {
   return launch_lincomb(y, y, 1.0, x, a, nullptr, 0.0, n, stream);
-}
-
-hipError_t launch_zero(double* y, int64_t n, hipStream_t stream) {
-  hipLaunchKernelGGL(zero_kernel, dim3(elem_grid(n)), dim3(256), 0, stream, y, n);
-  return hipGetLastError();
 }
 
 }  // namespace wcns

@@ -113,7 +113,8 @@ def test_workspace_size_covers_the_documented_buffers(L):
     try:
         elems = lib.wcns_state_elems(h)
         assert elems == 4 * 100 * 50
-        assert lib.wcns_workspace_bytes(h) >= 6 * 8 * elems
+        # two stage states, the residual accumulator, two stage cotangents
+        assert lib.wcns_workspace_bytes(h) >= 5 * 8 * elems
     finally:
         lib.wcns_plan_destroy(h)
 
