@@ -605,17 +605,14 @@ wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lam
     return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)work;
-  const int64_t len = plan->nv * plan->npts;
   double* U1 = (double*)(w + plan->off_W1);
   double* U2 = (double*)(w + plan->off_W2);
-  double* L = (double*)(w + plan->off_R);
+  double* Racc = (double*)(w + plan->off_R);
   wcns_status st;
-  // Recompute the stage states U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 (U1 + dt L(U1)).
-  if ((st = residual_into(plan, Un, L, s)) != WCNS_OK) return st;
-  WCNS_HIP(launch_lincomb(U1, Un, 1.0, L, 0.0, dt_dev, 1.0, len, s), "lincomb");
-  if ((st = residual_into(plan, U1, L, s)) != WCNS_OK) return st;
-  WCNS_HIP(launch_lincomb(U2, U1, 0.25, L, 0.0, dt_dev, 0.25, len, s), "lincomb");
-  WCNS_HIP(launch_axpy_state(U2, Un, 0.75, len, s), "axpy");
+  // Recompute the stage states U1 = Un + dt L(Un), U2 = 3/4 Un + 1/4 (U1 +
+  // dt L(U1)) with the forward step's own stage launches (bitwise the same).
+  if ((st = stage(plan, Un, Un, U1, 0.0, 1.0, dt_dev, Racc, nullptr, s)) != WCNS_OK) return st;
+  if ((st = stage(plan, U1, Un, U2, 0.75, 0.25, dt_dev, Racc, nullptr, s)) != WCNS_OK) return st;
   return rk3_adjoint_from_stages(plan, Un, U1, U2, lambda, work, dt_dev, stream);
 }
 

@@ -130,15 +130,15 @@ def test_rollout_gradient_independent_of_checkpoints(mods, W):
 
 def test_staged_rollout_gradient_equals_checkpointed(mods, W):
     """Stored stage states (no recomputation in the backward pass) give the
-    gradient of the checkpointed rollout: the stage states differ from the
-    recomputed ones only by the rounding of the fused stage combine."""
+    gradient of the checkpointed rollout bit for bit: the adjoint step
+    recomputes its stage states with the forward step's own launches."""
     solver, roll = mods
     prob, ctl, rho0, target, G, dt = _setup(solver, W, 128)
     say("staged rollout")
     J0, g0 = _loss_grad(G, roll, ctl, rho0, target, dt, 24, 5)
     J1, g1 = _loss_grad(G, roll, ctl, rho0, target, dt, 24, 5, stages=True)
     assert J1 == J0
-    assert float(torch.linalg.norm(g1 - g0)) <= 1e-11 * float(torch.linalg.norm(g0))
+    assert torch.equal(g1, g0)
 
 
 def _smooth_direction(gen, n, kmax=4):
