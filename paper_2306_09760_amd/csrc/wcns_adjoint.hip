@@ -1,5 +1,7 @@
-// Adjoint (vector-Jacobian product) of the WCNS-FE residual on gfx950:
-// Ubar += scale * (dL/dU)^T Rbar, one direction per launch.
+// Adjoint (vector-Jacobian product) of the WCNS-FE residual on gfx950, one
+// direction per launch: Ubar += s (dL/dU)^T Rbar, or, for the first direction
+// of a step's stage, Ubar = ca A + cb B + s (dL/dU)^T Rbar (s = scale, times
+// *dt when given; see AdjArgs).
 //
 // A workgroup of 256 lanes owns the nodes i0 .. i0+TL-1 (TL = TM - 5) of W
 // adjacent lines and recomputes the TM midpoints i0-3 .. i0+TL+1 whose
@@ -8,7 +10,8 @@
 // shape's scheduling).  Phases, separated by barriers:
 //   load     the TM+5 nodes of every column into LDS, ghosts applied;
 //   roe      Roe average per midpoint;
-//   interp   forward interpolation, one task per (side, field, midpoint);
+//   interp   forward interpolation, one task per (field, midpoint), both
+//            sides (interp5_pair);
 //   flux     per midpoint: flux cotangent from Rbar (transpose of the MND6 /
 //            MD6 difference), local Lax-Friedrichs VJP, back-projection VJP
 //            -> cotangents of the interpolated characteristic values and of
@@ -19,7 +22,7 @@
 //            in LDS) and the Roe-average VJP onto the two centre nodes;
 //   gather   per node: the six midpoint contributions, ghost positions folded
 //            onto the boundary node (transmissive), the node-flux term of
-//            MND6, and Ubar += scale * sum.
+//            MND6, and the epilogue above.
 // LDS (doubles): sU[NV][TM+5][W] | sR[NR][TMW] | sWB[6 NV][TMW] (its first
 // 2 NV rows hold the interpolated values and their cotangents first) | the
 // 64-entry exp table, TMW = TM W.  The Roe-quantity cotangent of a midpoint

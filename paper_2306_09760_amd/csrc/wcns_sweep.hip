@@ -5,23 +5,26 @@
 // direction by W adjacent x-columns (W = 1 for the x direction; for y and z
 // the columns make the global loads coalesced rows).  TM*W is 128 or 256 and
 // both are compile-time, so every LDS address is a lane base plus an
-// immediate offset.  Phases, separated by barriers, with every lane looping
-// over the phase's tasks (no wavefront idles through a short phase):
-//   load    the TM+5 nodes of every column into LDS, ghosts applied;
+// immediate offset.  Phases, with every lane looping over the phase's tasks
+// (no wavefront idles through a short phase):
+//   load    the TM+5 nodes of every column into LDS, ghosts applied (all
+//           global reads issued before the first LDS write);
 //   roe     Roe average of the two nodes around each midpoint;
-//   interp  one task = ONE nonlinear interpolation: field v of the
-//           left-biased or mirrored right-biased stencil of one midpoint,
-//           projected on the fly from the LDS nodes.  TM*W is a multiple of
-//           64, so the field and side are uniform across a wavefront;
+//   interp  one task = one field of one midpoint: its six stencil values
+//           projected on the fly from the LDS nodes, then the left-biased
+//           and the mirrored right-biased nonlinear interpolation
+//           (interp5_pair).  TM*W is a multiple of 64, so the field is
+//           uniform across a wavefront;
 //   flux    back-projection of the two interpolated states and the local
 //           Lax-Friedrichs flux;
 //   diff    MND6 or MD6 flux difference of TL = TM-3 (TM-5) nodes per
 //           column, written as R, R+= or the fused SSP-RK3 stage combine.
-// One interpolation per task keeps the live state small (under 100 VGPRs),
-// so the kernel runs several workgroups per CU.
-// LDS (doubles): sU[NV][TM+5][W] | sR[NR][TM*W] | sW[2 NV][TM*W]; the flux
-// overwrites sW rows 0..NV-1 (each task reads its midpoint's two states
-// before writing that midpoint's flux).
+// Barriers separate load | roe | interp | flux | diff; with TM*W = 256 every
+// lane owns one midpoint column through roe, interp and flux, and only
+// load | roe and flux | diff are synchronised.
+// LDS (doubles): sU[NV][TM+5][W] | sR[NR][TM*W] | sW[2 NV][TM*W] | the
+// 64-entry exp table; the flux overwrites sW rows 0..NV-1 (each task reads
+// its midpoint's two states before writing that midpoint's flux).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -51,8 +54,9 @@ struct SweepLayout {
 // The generic interpolation needs ~108 VGPRs and is left unconstrained
 // (capped at 80 it spills).
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_FE ? 6 : 1))) sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g,
-                                                    int mode) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_FE ? 6 : 1)))
+    sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g, int mode) {
   using L = SweepLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TN = L::TN, TMW = L::TMW, SV = L::SV;
   constexpr int LW = L::LW, LTMW = L::LTMW;
