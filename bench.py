@@ -44,6 +44,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the xi = 1e6 and plain-form (1D per problem, 2D, 3D) timings")
+    ap.add_argument("--tile", type=int, choices=[128, 256], default=None,
+                    help="midpoints per batch tile instead of the autotuner's choice "
+                         "(keeps profiled runs, where timings shift, on one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -168,7 +171,10 @@ def main():
     B = BatchPlan(meta["offsets"], meta["h"], **proto)
     U0 = torch.from_numpy(U_host).to(dev)
     U = U0.clone()
-    tile = B.autotune(U)
+    if args.tile is None:
+        tile = B.autotune(U)
+    else:
+        B.tile = tile = args.tile
     B.set_graph(not args.no_graph)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
 
