@@ -248,6 +248,43 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    def time_launches(fn, n):
+        """Average ms of n calls after one warm call (HIP events, current stream)."""
+        fn()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record()
+        for _ in range(n):
+            fn()
+        f1.record()
+        torch.cuda.synchronize()
+        return f0.elapsed_time(f1) / n
+
+    # ---- roof probes: FP64 FMA stream and HBM streaming copy ----------------
+    from paper_2306_09760_amd._lib import check as _check, lib as _lib
+    stream = torch.cuda.current_stream().cuda_stream
+    pblocks, piters = 2048, 20000
+    pout = torch.empty(pblocks * 256, dtype=torch.float64, device=dev)
+    ncopy = 1 << 27  # 1 GiB of doubles
+    psrc = torch.ones(ncopy, dtype=torch.float64, device=dev)
+    pdst = torch.empty_like(psrc)
+
+    def run_fma():
+        _check(_lib().wcns_probe_fp64_fma(pout.data_ptr(), pblocks, piters, stream), "probe")
+
+    def run_copy():
+        _check(_lib().wcns_probe_copy(psrc.data_ptr(), pdst.data_ptr(), ncopy, stream), "probe")
+
+    fma_ms = time_launches(run_fma, 3)
+    copy_ms = time_launches(run_copy, 5)
+    fma_tf = pblocks * 256 * piters * 16 / (fma_ms * 1e-3) / 1e12
+    copy_tbs = 16 * ncopy / (copy_ms * 1e-3) / 1e12
+    probes = {"fp64_fma_tflops": round(fma_tf, 2), "fp64_fma_frac_of_published": round(fma_tf / PEAK_FP64_TFLOPS, 3),
+              "copy_tbps": round(copy_tbs, 3), "copy_frac_of_published": round(copy_tbs * 1e3 / PEAK_HBM_GBS, 3),
+              "stage_kernel_frac_of_probe_fp64": round(achieved_tflops / fma_tf, 3),
+              "note": "register-resident FP64 FMA chains (2048 x 256 lanes) and a 1 GiB "
+                      "16-byte streaming copy, timed with HIP events"}
+    del pout, psrc, pdst
+
     # ---- adjoint / forward time on the 2D periodic problem ----------------
     adjoint = None
     if not args.no_adjoint:
@@ -332,16 +369,6 @@ def main():
     # ---- other forms on the same GPU --------------------------------------
     forms = None
     if not args.no_forms:
-        def time_launches(fn, n):
-            fn()
-            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            f0.record()
-            for _ in range(n):
-                fn()
-            f1.record()
-            torch.cuda.synchronize()
-            return f0.elapsed_time(f1) / n
-
         forms = {"batch_stage_xi_%g" % args.xi: {
             "kernel_ms": round(kernel_ms, 4), "pt_stage_per_s": total_pts / (kernel_ms * 1e-3)}}
         # the batch at xi = 1e6: per-term exponentials (generic instantiation)
@@ -431,6 +458,7 @@ def main():
             "fp64_share_of_valu": (cnt["fp64_wave_insts"] / cnt["valu_wave_insts"]) if cnt else None,
         },
         "cpu_baseline": cpu,
+        "probes": probes,
         "adjoint_forward": adjoint,
         "forms": forms,
         "status_word": bad,

@@ -247,6 +247,19 @@ wcns_status wcns_batch_autotune(wcns_batch_plan* plan, const double* U, void* wo
 int32_t wcns_batch_get_tile(const wcns_batch_plan* plan);
 wcns_status wcns_batch_set_tile(wcns_batch_plan* plan, int32_t tile);
 
+/* ----- roof probes (measurement of the machine, not part of the method) -- */
+/* FP64 vector-FMA throughput: `blocks` workgroups of 256 lanes each run
+   `iters` rounds of eight independent chains x <- fma(x, 1 - 2^-30, 2^-30)
+   (16 flops per lane per round) from x0 = 1 + (g mod 1024)/1024 + k/16
+   (g the lane's global index, k the chain) and write each lane's sum of its
+   chains to out[g] (device, blocks * 256 doubles).  The caller times it.
+   WCNS_EINVAL for a NULL out or blocks, iters < 1. */
+wcns_status wcns_probe_fp64_fma(double* out, int32_t blocks, int32_t iters, void* stream);
+/* HBM streaming copy dst[i] = src[i], i < n, 16 bytes per lane per access
+   (device arrays, 16-byte aligned, not overlapping; WCNS_EINVAL otherwise).
+   The caller times it: 16 n bytes move. */
+wcns_status wcns_probe_copy(const double* src, double* dst, int64_t n, void* stream);
+
 const char* wcns_status_string(wcns_status s);
 /* Message of the last failing call on this host thread ("" if none). */
 const char* wcns_last_error(void);

@@ -34,7 +34,8 @@ EXPORTS = [
     "wcns_batch_plan_destroy", "wcns_batch_state_elems", "wcns_batch_workspace_bytes",
     "wcns_batch_residual", "wcns_batch_rk3_step", "wcns_batch_set_graph",
     "wcns_batch_autotune", "wcns_batch_get_tile", "wcns_batch_set_tile",
-    "wcns_batch_cfl", "wcns_batch_stage", "wcns_status_string", "wcns_last_error",
+    "wcns_batch_cfl", "wcns_batch_stage", "wcns_probe_fp64_fma", "wcns_probe_copy",
+    "wcns_status_string", "wcns_last_error",
 ]
 
 
@@ -98,6 +99,8 @@ def lib():
         "wcns_batch_autotune": (st, [vp, vp, vp, vp]),
         "wcns_batch_get_tile": (C.c_int32, [vp]),
         "wcns_batch_set_tile": (st, [vp, C.c_int32]),
+        "wcns_probe_fp64_fma": (st, [vp, C.c_int32, C.c_int32, vp]),
+        "wcns_probe_copy": (st, [vp, vp, C.c_int64, vp]),
         "wcns_status_string": (C.c_char_p, [st]),
         "wcns_last_error": (C.c_char_p, []),
     }

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libwcns.so")
 SOURCES = ["wcns_api.hip", "wcns_kernels.hip", "wcns_sweep.hip", "wcns_adjoint.hip",
-           "wcns_stats.hip", "wcns_weno.hip"]
+           "wcns_stats.hip", "wcns_weno.hip", "wcns_probe.hip"]
 ARCH = os.environ.get("WCNS_OFFLOAD_ARCH", "gfx950")
 
 

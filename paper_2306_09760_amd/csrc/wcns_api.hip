@@ -994,6 +994,25 @@ wcns_status wcns_batch_autotune(wcns_batch_plan* B, const double* U, void* work,
   return wcns_batch_set_tile(B, best_tm);
 }
 
+wcns_status wcns_probe_fp64_fma(double* out, int32_t blocks, int32_t iters, void* stream) {
+  g_err.clear();
+  if (!out) return fail(WCNS_EINVAL, "NULL argument");
+  if (blocks < 1 || iters < 1) return fail(WCNS_EINVAL, "blocks and iters must be >= 1");
+  WCNS_HIP(launch_probe_fma(out, blocks, iters, (hipStream_t)stream), "probe launch");
+  return WCNS_OK;
+}
+
+wcns_status wcns_probe_copy(const double* src, double* dst, int64_t n, void* stream) {
+  g_err.clear();
+  if (!src || !dst) return fail(WCNS_EINVAL, "NULL argument");
+  if (n < 0) return fail(WCNS_EINVAL, "n must be >= 0");
+  if (((uintptr_t)src | (uintptr_t)dst) & 15) return fail(WCNS_EINVAL, "src and dst must be 16-byte aligned");
+  const double *s0 = src, *s1 = src + n, *d0 = dst, *d1 = dst + n;
+  if (n > 0 && s0 < d1 && d0 < s1) return fail(WCNS_EINVAL, "src and dst overlap");
+  WCNS_HIP(launch_probe_copy(src, dst, n, (hipStream_t)stream), "probe launch");
+  return WCNS_OK;
+}
+
 const char* wcns_status_string(wcns_status s) {
   switch (s) {
     case WCNS_OK: return "ok";

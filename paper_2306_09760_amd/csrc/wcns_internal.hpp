@@ -105,4 +105,7 @@ hipError_t launch_adjoint_dir(int nv, int dir, const AdjArgs& a, hipStream_t str
 
 int cfl_blocks(int64_t npts);
 
+hipError_t launch_probe_fma(double* out, int blocks, int iters, hipStream_t stream);
+hipError_t launch_probe_copy(const double* src, double* dst, int64_t n, hipStream_t stream);
+
 }  // namespace wcns
