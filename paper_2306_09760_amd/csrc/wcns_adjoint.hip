@@ -24,8 +24,9 @@
 //            onto the boundary node (transmissive), the node-flux term of
 //            MND6, and the epilogue above.
 // LDS (doubles): sU[NV][TM+5][W] | sR[NR][TMW] | sWB[6 NV][TMW] (its first
-// 2 NV rows hold the interpolated values and their cotangents first) | the
-// 64-entry exp table, TMW = TM W.  The Roe-quantity cotangent of a midpoint
+// 2 NV rows hold the interpolated values and their cotangents first, the
+// rest Rbar of the tile's nodes until the interpolation VJP) | the 64-entry
+// exp table, TMW = TM W.  The Roe-quantity cotangent of a midpoint
 // stays in its lane's registers from the flux VJP to the projection VJP.
 #include <hip/hip_runtime.h>
 
@@ -116,7 +117,12 @@ __global__ void __launch_bounds__(256)
   // load: all global reads of the tile issued before the first LDS write
   constexpr int NIT = (SV + NT - 1) / NT;
   static_assert(NIT <= 2, "a tile holds at most two nodes per lane");
-  double buf[NIT][NV];
+  // Rbar of the same nodes (the transposed difference of the flux VJP reads
+  // nodes m-2 .. m+3 of every midpoint m) goes to sWB rows 2 NV .. 6 NV - 1,
+  // which stay unused until the interpolation VJP.
+  double* sRB = sWB + 2 * NV * TMW;
+  static_assert(NV * SV <= 4 * NV * TMW, "Rbar staging exceeds the free sWB rows");
+  double buf[NIT][NV], rbuf[NIT][NV];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int idx = tid + it * NT;
@@ -126,6 +132,9 @@ __global__ void __launch_bounds__(256)
       const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
 #pragma unroll
       for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        rbuf[it][v] = rbar_at(a.Rbar + v * a.npts, base + cc, stride, nb + k, N, a.bc);
     }
   }
   double xv = 0.0;
@@ -137,7 +146,10 @@ __global__ void __launch_bounds__(256)
     const int idx = tid + it * NT;
     if (idx < SV) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sU[v * SV + idx] = buf[it][v];
+      for (int v = 0; v < NV; ++v) {
+        sU[v * SV + idx] = buf[it][v];
+        sRB[v * SV + idx] = rbuf[it][v];
+      }
     }
   }
   if constexpr (TAB) {
@@ -239,23 +251,17 @@ __global__ void __launch_bounds__(256)
   if (tid < TMW) {
     const int q = tid;
     const int t = q >> LW, c = q & (W - 1);
-    const int cc = c < ncol ? c : ncol - 1;
-    const int64_t m = i0 - 3 + t;
-    const int64_t lb = base + cc;
     double Fb[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const double* Rb = a.Rbar + v * a.npts;
-      const double r0 = rbar_at(Rb, lb, stride, m, N, a.bc);
-      const double r1 = rbar_at(Rb, lb, stride, m + 1, N, a.bc);
-      const double rm1 = rbar_at(Rb, lb, stride, m - 1, N, a.bc);
-      const double r2 = rbar_at(Rb, lb, stride, m + 2, N, a.bc);
+      // Rbar at node m + d (m = i0 - 3 + t) is staged at LDS node t + 2 + d
+      const double* Rb = sRB + v * SV + t * W + c;
+      const double r0 = Rb[2 * W], r1 = Rb[3 * W], rm1 = Rb[W], r2 = Rb[4 * W];
       double d;
       if (a.diff == 0) {
         d = 1.5 * (r0 - r1) + (1.0 / 30.0) * (rm1 - r2);
       } else {
-        const double rm2 = rbar_at(Rb, lb, stride, m - 2, N, a.bc);
-        const double r3 = rbar_at(Rb, lb, stride, m + 3, N, a.bc);
+        const double rm2 = Rb[0], r3 = Rb[5 * W];
         d = (75.0 / 64.0) * (r0 - r1) + (-25.0 / 384.0) * (rm1 - r2) + (3.0 / 640.0) * (rm2 - r3);
       }
       Fb[v] = -a.ih * d;
