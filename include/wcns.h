@@ -199,7 +199,7 @@ void wcns_plan_get_tiles(const wcns_plan* plan, int32_t tiles[3]);
    would exceed 64 KB of LDS for this system). */
 wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]);
 
-/* ----- ragged batch of independent 1D problems (one persistent launch per
+/* ----- ragged batch of independent 1D problems (one launch per
    stage; one graph-captured step) --------------------------------------- */
 /* proto: a 1D descriptor (its n[0] and h[0] are ignored).  Problem p holds
    offsets_host[p+1] - offsets_host[p] >= 9 nodes at columns

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -203,8 +204,8 @@ struct wcns_batch_plan {
   std::vector<double> h_ih;
   int64_t* d_offset = nullptr;
   double* d_ih = nullptr;
-  int32_t* d_tile_prob = nullptr;
-  int32_t* d_tile_i0 = nullptr;
+  int32_t* d_tile_p0 = nullptr;
+  int32_t* d_tile_p1 = nullptr;
   int32_t ntiles = 0;
   int tm = 128;
   int grid = 0;
@@ -701,31 +702,35 @@ wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, voi
 // ------------------------------------------------------------------ batch --
 
 static wcns_status batch_build_tiles(wcns_batch_plan* B) {
+  // Packed tiles over the virtual index space of the problems laid end to
+  // end with 2G ghost slots each (BatchArgs): all tiles are full, so only the
+  // 2G slots per problem compute midpoints that no node uses.
+  const int G = B->d.diff ? 5 : 4;
   const int TL = B->tm - (B->d.diff ? 5 : 3);
-  struct T { int32_t p, i0, len; };
-  std::vector<T> tiles;
-  for (int64_t p = 0; p < B->nprob; ++p) {
-    const int64_t N = B->h_offset[p + 1] - B->h_offset[p];
-    for (int64_t i0 = 0; i0 < N; i0 += TL)
-      tiles.push_back(T{(int32_t)p, (int32_t)i0, (int32_t)std::min<int64_t>(TL, N - i0)});
+  const int64_t np = B->nprob;
+  auto start = [&](int64_t p) { return B->h_offset[p] + 2 * G * p; };
+  const int64_t V = start(np);
+  const int64_t nt = (V + TL - 1) / TL;
+  if (nt > INT32_MAX) return fail(WCNS_EUNSUPPORTED, "batch needs %lld tiles", (long long)nt);
+  std::vector<int32_t> tp((size_t)nt), tq((size_t)nt);
+  int64_t p = 0, q = 0;  // problems holding the first and the last slot of tile k
+  for (int64_t k = 0; k < nt; ++k) {
+    const int64_t lo = k * TL - G, hi = k * TL + TL + G - 1;
+    while (p + 1 < np && start(p + 1) <= lo) ++p;
+    while (q + 1 < np && start(q + 1) <= hi) ++q;
+    tp[(size_t)k] = (int32_t)p;
+    tq[(size_t)k] = (int32_t)q;
   }
-  // Longest-first: full tiles before the ragged last tile of each problem.
-  std::stable_sort(tiles.begin(), tiles.end(), [](const T& a, const T& b) { return a.len > b.len; });
-  std::vector<int32_t> tp(tiles.size()), ti(tiles.size());
-  for (size_t k = 0; k < tiles.size(); ++k) {
-    tp[k] = tiles[k].p;
-    ti[k] = tiles[k].i0;
-  }
-  if (B->d_tile_prob) hipFree(B->d_tile_prob);
-  if (B->d_tile_i0) hipFree(B->d_tile_i0);
-  B->d_tile_prob = nullptr;
-  B->d_tile_i0 = nullptr;
-  B->ntiles = (int32_t)tiles.size();
-  WCNS_HIP(hipMalloc(&B->d_tile_prob, sizeof(int32_t) * tiles.size()), "hipMalloc tiles");
-  WCNS_HIP(hipMalloc(&B->d_tile_i0, sizeof(int32_t) * tiles.size()), "hipMalloc tiles");
-  WCNS_HIP(hipMemcpy(B->d_tile_prob, tp.data(), sizeof(int32_t) * tp.size(), hipMemcpyHostToDevice), "copy tiles");
-  WCNS_HIP(hipMemcpy(B->d_tile_i0, ti.data(), sizeof(int32_t) * ti.size(), hipMemcpyHostToDevice), "copy tiles");
-  // Persistent grid: enough resident workgroups to fill every CU a few times.
+  if (B->d_tile_p0) hipFree(B->d_tile_p0);
+  if (B->d_tile_p1) hipFree(B->d_tile_p1);
+  B->d_tile_p0 = nullptr;
+  B->d_tile_p1 = nullptr;
+  B->ntiles = (int32_t)nt;
+  WCNS_HIP(hipMalloc(&B->d_tile_p0, sizeof(int32_t) * tp.size()), "hipMalloc tiles");
+  WCNS_HIP(hipMalloc(&B->d_tile_p1, sizeof(int32_t) * tq.size()), "hipMalloc tiles");
+  WCNS_HIP(hipMemcpy(B->d_tile_p0, tp.data(), sizeof(int32_t) * tp.size(), hipMemcpyHostToDevice), "copy tiles");
+  WCNS_HIP(hipMemcpy(B->d_tile_p1, tq.data(), sizeof(int32_t) * tq.size(), hipMemcpyHostToDevice), "copy tiles");
+  // one workgroup per tile
   B->grid = B->ntiles;
   if (B->exec) {
     hipGraphExecDestroy(B->exec);
@@ -789,8 +794,8 @@ wcns_status wcns_batch_plan_destroy(wcns_batch_plan* B) {
   if (B->cap_stream) hipStreamDestroy(B->cap_stream);
   if (B->d_offset) hipFree(B->d_offset);
   if (B->d_ih) hipFree(B->d_ih);
-  if (B->d_tile_prob) hipFree(B->d_tile_prob);
-  if (B->d_tile_i0) hipFree(B->d_tile_i0);
+  if (B->d_tile_p0) hipFree(B->d_tile_p0);
+  if (B->d_tile_p1) hipFree(B->d_tile_p1);
   delete B;
   return WCNS_OK;
 }
@@ -814,8 +819,8 @@ static void batch_args(const wcns_batch_plan* B, double* dtp, SweepArgs* a, Batc
   b->offset = B->d_offset;
   b->ih = B->d_ih;
   b->dtp = dtp;
-  b->tile_prob = B->d_tile_prob;
-  b->tile_i0 = B->d_tile_i0;
+  b->tile_p0 = B->d_tile_p0;
+  b->tile_p1 = B->d_tile_p1;
   b->ntiles = B->ntiles;
   b->nprob = (int32_t)B->nprob;
 }

@@ -38,12 +38,16 @@ struct SweepArgs {
 };
 
 // Ragged batch description (device arrays).
+// Batch tiles are packed: problem p occupies the slots [s_p, s_p + N_p + 2G)
+// of a virtual index space, s_p = offset[p] + 2 G p (G ghost slots on each
+// side of its nodes), and tile k outputs the slots [k TL, k TL + TL), so a
+// tile may span the end of one problem and the start of the next.
 struct BatchArgs {
   const int64_t* offset;   // nprob+1 column offsets
   const double* ih;        // 1/h per problem
   double* dtp;             // per-problem dt of the current step (0 = inactive)
-  const int32_t* tile_prob;
-  const int32_t* tile_i0;
+  const int32_t* tile_p0;  // first and last problem that the slots a tile
+  const int32_t* tile_p1;  //   loads (outputs and halo) touch
   int32_t ntiles;
   int32_t nprob;
 };

@@ -19,6 +19,9 @@
 //           Lax-Friedrichs flux;
 //   diff    MND6 or MD6 flux difference of TL = TM-3 (TM-5) nodes per
 //           column, written as R, R+= or the fused SSP-RK3 stage combine.
+// The ragged batch packs its tiles across problem ends (BatchArgs): a tile's
+// slots may belong to two or more problems, each slot mapped to its problem,
+// node or ghost in the load phase.
 // Barriers separate load | roe | interp | flux | diff; with TM*W = 256 every
 // lane owns one midpoint column through roe, interp and flux, and only
 // load | roe and flux | diff are synchronised.
@@ -72,19 +75,20 @@ __global__ void __launch_bounds__(256)
 
   const int64_t tile = blockIdx.x;
   if (tile >= g.ntiles) return;
-  int64_t base, N, stride, i0;
+  int64_t base = 0, N = 0, stride = 1, i0;
   int ncol = 1;
   double ih = a.ih, dt = 0.0;
+  BatchTile bt{};
+  bool near = true;  // the tile spans at most two problems
   if constexpr (BATCH) {
-    const int p = b.tile_prob[tile];
-    base = b.offset[p];
-    N = b.offset[p + 1] - base;
-    stride = 1;
-    i0 = b.tile_i0[tile];
-    ih = b.ih[p];
+    // i0 is a slot of the packed index space (BatchArgs)
+    i0 = tile * TL;
+    bt = batch_tile(b, tile, i0, G);
+    near = bt.p1 <= bt.p0 + 1;
     if (mode == MODE_STAGE) {
-      dt = b.dtp[p];
-      if (dt == 0.0) return;  // finished problem: uniform across the block
+      bool live = false;  // uniform across the block
+      for (int p = bt.p0; p <= bt.p1; ++p) live |= (b.dtp[p] != 0.0);
+      if (!live) return;  // every problem of the tile has finished
     }
   } else {
     const int64_t seg = tile % g.segs;
@@ -125,9 +129,33 @@ __global__ void __launch_bounds__(256)
     if (idx < SV) {
       const int k = idx >> LW, c = idx & (W - 1);
       const int cc = c < ncol ? c : ncol - 1;
-      const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+      int64_t gi;
+      if constexpr (BATCH) {
+        const BatchSlot sl =
+            near ? batch_slot_near(bt, k - G) : batch_slot(b, bt.p0, bt.p1, G, nb + k);
+        // slots outside every problem's range (before the first, after the
+        // last) load a ghost; no output node uses them
+        const int j = sl.j < -G ? -G : (sl.j >= sl.n + G ? sl.n + G - 1 : sl.j);
+        gi = sl.o + bc_index_near(j, sl.n, a.bc);
+      } else {
+        gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
+    }
+  }
+  // the lane's output node in a batch tile (-1: none, or a ghost slot)
+  int64_t onode = -1;
+  int oprob = 0;
+  if constexpr (BATCH) {
+    static_assert(W == 1 && TM <= NT, "one output node per lane");
+    if (tid < TL) {
+      const BatchSlot sl =
+          near ? batch_slot_near(bt, tid) : batch_slot(b, bt.p0, bt.p1, G, i0 + tid);
+      if (sl.j >= 0 && sl.j < sl.n) {
+        onode = sl.o + sl.j;
+        oprob = sl.p;
+      }
     }
   }
   double xv = 0.0;
@@ -219,6 +247,18 @@ __global__ void __launch_bounds__(256)
   }
   if constexpr (!OWN) __syncthreads();
 
+  // A batch tile has at most one output node per lane (TL < 256): the lane
+  // locates it during the load phase and reads its problem's 1/h and dt
+  // here, so that these reads overlap the flux phase rather than the
+  // epilogue.
+  double oih = 0.0, odt = 0.0;
+  if constexpr (BATCH) {
+    if (onode >= 0) {
+      oih = b.ih[oprob];
+      if (mode == MODE_STAGE) odt = b.dtp[oprob];
+    }
+  }
+
   // midpoint flux (overwrites sW rows 0..NV-1 of the same midpoint)
 #pragma unroll 1
   for (int q = tid; q < TMW; q += NT) {
@@ -262,8 +302,18 @@ __global__ void __launch_bounds__(256)
 #pragma unroll 1
   for (int q = tid; q < TL * W; q += NT) {
     const int t = q >> LW, c = q & (W - 1);
-    const int64_t i = i0 + t;
-    if (i >= N || c >= ncol) continue;
+    int64_t i = i0 + t;
+    if constexpr (BATCH) {
+      // q == tid here (one output node per lane)
+      if (onode < 0) continue;  // a ghost slot
+      dt = odt;
+      if (mode == MODE_STAGE && dt == 0.0) continue;  // finished problem
+      ih = oih;
+      base = onode;
+      i = 0;
+    } else {
+      if (i >= N || c >= ncol) continue;
+    }
     const double* f = sW + q;        // F~ of midpoint t + k of column c at f[k W]
     const double* u = sU + q;        // node t + k of column c at u[k W]
     double res[NV], Un[NV];

@@ -21,6 +21,71 @@ __device__ __forceinline__ int64_t bc_index(int64_t j, int64_t N, int bc) {
   return j < 0 ? 0 : (j >= N ? N - 1 : j);  // transmissive: zeroth-order copy
 }
 
+// Slot v of a packed batch (BatchArgs) as problem p, its first node o in the
+// state arrays, its length n and the node index j = v - s_p - G (negative or
+// >= n for a ghost slot).  p0 .. p1 bound the problems the caller's slots
+// can touch; slots outside all ranges come out with j < -G or j >= n + G.
+struct BatchSlot {
+  int64_t o;
+  int n, j, p;
+};
+__device__ __forceinline__ BatchSlot batch_slot(const BatchArgs& b, int p0, int p1, int G,
+                                                int64_t v) {
+  int p = p0;
+  int64_t o = b.offset[p], e = b.offset[p + 1];
+  while (p < p1 && v >= e + 2 * (int64_t)G * (p + 1)) {
+    ++p;
+    o = e;
+    e = b.offset[p + 1];
+  }
+  return BatchSlot{o, (int)(e - o), (int)(v - o - 2 * (int64_t)G * p - G), p};
+}
+
+// A tile of a packed batch, from uniform reads: its problems p0 .. p1 and,
+// for the common case p1 <= p0 + 1, what maps a tile-relative slot r (slot
+// i0 + r, r in [-G, TL + G)) to its problem in 32-bit arithmetic.
+struct BatchTile {
+  int p0, p1;
+  int64_t o0, o1;  // first nodes of p0 and p0 + 1
+  int n0, n1;      // their lengths
+  int c0, c1;      // node index of slot i0 + r: r + c0 in p0, r + c1 in p0 + 1
+  int r1;          // first relative slot of p0 + 1 (beyond every r if p1 == p0)
+};
+__device__ __forceinline__ BatchTile batch_tile(const BatchArgs& b, int64_t tile, int64_t i0,
+                                                int G) {
+  BatchTile t;
+  t.p0 = b.tile_p0[tile];
+  t.p1 = b.tile_p1[tile];
+  t.o0 = b.offset[t.p0];
+  t.o1 = b.offset[t.p0 + 1];
+  t.n0 = (int)(t.o1 - t.o0);
+  // slot i0 - G lies in p0's range (or before the first problem), so
+  // c0 = i0 - s0 - G is in [-G, n0 + 2G)
+  t.c0 = (int)(i0 - (t.o0 + 2 * (int64_t)G * t.p0) - G);
+  if (t.p1 > t.p0) {
+    const int64_t o2 = b.offset[t.p0 + 2];
+    t.n1 = (int)(o2 - t.o1);
+    // p0 + 1 starts within the tile's slots: r1 in (-G, TL + G]
+    t.r1 = (int)(t.o1 + 2 * (int64_t)G * (t.p0 + 1) - i0);
+    t.c1 = -t.r1 - G;
+  } else {
+    t.n1 = t.n0;
+    t.r1 = 1 << 30;
+    t.c1 = t.c0;
+  }
+  return t;
+}
+__device__ __forceinline__ BatchSlot batch_slot_near(const BatchTile& t, int r) {
+  const bool s = r >= t.r1;
+  return BatchSlot{s ? t.o1 : t.o0, s ? t.n1 : t.n0, r + (s ? t.c1 : t.c0), t.p0 + (int)s};
+}
+
+// bc_index for a node index within [-G, n + G) of a problem of n > G nodes
+__device__ __forceinline__ int bc_index_near(int j, int n, int bc) {
+  if (bc == 0) return j < 0 ? j + n : (j >= n ? j - n : j);
+  return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
 __device__ __forceinline__ void flag_status(int32_t* status) {
   if (status) atomicOr(status, 1);
 }

@@ -1,4 +1,4 @@
-"""Ragged batch of independent 1D Euler problems (one persistent launch per
+"""Ragged batch of independent 1D Euler problems (one launch per
 stage, graph-captured step) against the oracle run problem by problem."""
 import numpy as np
 import pytest
@@ -20,9 +20,9 @@ def _small_batch(W, seed=0, nprob=12, nmin=9, nmax=700):
     return W.shock_tube_batch(seed=seed, nprob=nprob, nmin=nmin, nmax=nmax)
 
 
-def _oracle(ora, meta, p, **kw):
+def _oracle(ora, meta, p, bc="transmissive", **kw):
     N = int(meta["lengths"][p])
-    return ora.Problem(system="euler", ndim=1, n=(N,), h=(meta["h"][p],), bc="transmissive", **kw)
+    return ora.Problem(system="euler", ndim=1, n=(N,), h=(meta["h"][p],), bc=bc, **kw)
 
 
 def _cols(U, meta, p):
@@ -40,6 +40,23 @@ def test_batch_residual(lib, ora, W, weights, xi, tile):
     R = to_host(B.residual(to_dev(U)))
     for p in range(len(meta["lengths"])):
         ref = _oracle(ora, meta, p, weights=weights, xi=xi).residual(_cols(U, meta, p))
+        n, pt = rel_err(_cols(R, meta, p), ref)
+        assert n <= 1e-12 and pt <= 1e-10, (p, n, pt)
+
+
+@pytest.mark.parametrize("diff", ["mnd6", "md6"])
+@pytest.mark.parametrize("bc", ["transmissive", "periodic"])
+@pytest.mark.parametrize("tile", [128, 256])
+def test_batch_residual_short_problems(lib, ora, W, diff, bc, tile):
+    """Problems of 9 to 40 nodes: tiles are packed across problem ends, so
+    every tile holds the nodes and ghost slots of several problems."""
+    prob, U, meta = _small_batch(W, seed=4, nprob=64, nmin=9, nmax=40)
+    say("batch residual, short problems", diff, bc, tile)
+    B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0, diff=diff, bc=bc)
+    B.tile = tile
+    R = to_host(B.residual(to_dev(U)))
+    for p in range(len(meta["lengths"])):
+        ref = _oracle(ora, meta, p, bc=bc, weights="fe", xi=100.0, diff=diff).residual(_cols(U, meta, p))
         n, pt = rel_err(_cols(R, meta, p), ref)
         assert n <= 1e-12 and pt <= 1e-10, (p, n, pt)
 
@@ -87,7 +104,10 @@ def test_graph_replay_equals_eager_steps(lib, W):
         assert np.array_equal(a, b)
 
 
-def test_finished_problems_are_untouched(lib, W):
+def test_finished_problems_are_untouched(lib, ora, W):
+    """A finished problem shares its tiles with live neighbours (tiles are
+    packed across problem ends): it stays bitwise unchanged, they advance one
+    step as the oracle does."""
     prob, U, meta = _small_batch(W, seed=3, nprob=6, nmin=50, nmax=80)
     say("finished problems")
     B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
@@ -97,7 +117,12 @@ def test_finished_problems_are_untouched(lib, W):
     B.rk3_step(Ud, t, 0.1, 0.5)
     Ug = to_host(Ud)
     assert np.array_equal(_cols(Ug, meta, 2), _cols(U, meta, 2))
-    assert not np.array_equal(_cols(Ug, meta, 0), _cols(U, meta, 0))
+    for p in (0, 1, 3, 4, 5):
+        O = _oracle(ora, meta, p, weights="fe", xi=100.0)
+        dt = min(O.cfl_dt(_cols(U, meta, p), 0.5), 0.1)
+        U1, bad = O.rk3_step(_cols(U, meta, p), dt)
+        n, pt = rel_err(_cols(Ug, meta, p), U1)
+        assert n <= 1e-12 and pt <= 1e-12, (p, n, pt)
 
 
 def test_full_config2_batch_sampled(lib, ora, W):
