@@ -60,6 +60,10 @@ struct TileGeom {
   int64_t segs;          // tiles along one line
   int64_t xgroups;       // column groups across x (1 along x)
   int64_t ntiles;
+  // x sweep of the sweep kernel: the x-lines packed end to end like a batch
+  // of equal problems (line r at slots [r L, (r+1) L), L = n[0] + 2G)
+  int64_t lines;
+  double inv_line;       // 1 / L
 };
 
 // Launchers.  All enqueue on `stream` and return the hipError_t of the launch

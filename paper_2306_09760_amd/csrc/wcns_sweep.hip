@@ -78,10 +78,12 @@ __global__ void __launch_bounds__(256)
   int64_t base = 0, N = 0, stride = 1, i0;
   int ncol = 1;
   double ih = a.ih, dt = 0.0;
+  // Along x (and in the batch) the lines are packed end to end: i0 is a slot
+  // of the packed index space (BatchArgs, TileGeom::lines).
+  constexpr bool LINES = BATCH || DIR == 0;
   BatchTile bt{};
-  bool near = true;  // the tile spans at most two problems
+  bool near = true;  // the tile spans at most two lines or problems
   if constexpr (BATCH) {
-    // i0 is a slot of the packed index space (BatchArgs)
     i0 = tile * TL;
     bt = batch_tile(b, tile, i0, G);
     near = bt.p1 <= bt.p0 + 1;
@@ -90,28 +92,28 @@ __global__ void __launch_bounds__(256)
       for (int p = bt.p0; p <= bt.p1; ++p) live |= (b.dtp[p] != 0.0);
       if (!live) return;  // every problem of the tile has finished
     }
+  } else if constexpr (DIR == 0) {
+    i0 = tile * TL;
+    N = a.n[0];
+    bt = line_tile(i0, N, g.lines, G, TL, g.inv_line);
+    near = bt.p1 <= bt.p0 + 1;
+    if (mode >= MODE_STAGE) dt = *a.dt;
   } else {
     const int64_t seg = tile % g.segs;
     const int64_t r = tile / g.segs;
     i0 = seg * TL;
-    if constexpr (DIR == 0) {
-      N = a.n[0];
-      base = r * N;
-      stride = 1;
+    const int64_t xg = r % g.xgroups;
+    const int64_t other = r / g.xgroups;
+    const int64_t x0 = xg * W;
+    ncol = (int)((a.n[0] - x0) < W ? (a.n[0] - x0) : W);
+    if constexpr (DIR == 1) {
+      N = a.n[1];
+      stride = a.n[0];
+      base = x0 + other * a.n[0] * a.n[1];
     } else {
-      const int64_t xg = r % g.xgroups;
-      const int64_t other = r / g.xgroups;
-      const int64_t x0 = xg * W;
-      ncol = (int)((a.n[0] - x0) < W ? (a.n[0] - x0) : W);
-      if constexpr (DIR == 1) {
-        N = a.n[1];
-        stride = a.n[0];
-        base = x0 + other * a.n[0] * a.n[1];
-      } else {
-        N = a.n[2];
-        stride = a.n[0] * a.n[1];
-        base = x0 + other * a.n[0];
-      }
+      N = a.n[2];
+      stride = a.n[0] * a.n[1];
+      base = x0 + other * a.n[0];
     }
     if (mode >= MODE_STAGE) dt = *a.dt;
   }
@@ -130,9 +132,14 @@ __global__ void __launch_bounds__(256)
       const int k = idx >> LW, c = idx & (W - 1);
       const int cc = c < ncol ? c : ncol - 1;
       int64_t gi;
-      if constexpr (BATCH) {
-        const BatchSlot sl =
-            near ? batch_slot_near(bt, k - G) : batch_slot(b, bt.p0, bt.p1, G, nb + k);
+      if constexpr (LINES) {
+        BatchSlot sl;
+        if (near)
+          sl = batch_slot_near(bt, k - G);
+        else if constexpr (BATCH)
+          sl = batch_slot(b, bt.p0, bt.p1, G, nb + k);
+        else
+          sl = line_slot(nb + k, N, g.lines, G, g.inv_line);
         // slots outside every problem's range (before the first, after the
         // last) load a ghost; no output node uses them
         const int j = sl.j < -G ? -G : (sl.j >= sl.n + G ? sl.n + G - 1 : sl.j);
@@ -144,14 +151,20 @@ __global__ void __launch_bounds__(256)
       for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
     }
   }
-  // the lane's output node in a batch tile (-1: none, or a ghost slot)
+  // the lane's output node in a tile of packed lines (-1: none, or a ghost
+  // slot)
   int64_t onode = -1;
   int oprob = 0;
-  if constexpr (BATCH) {
+  if constexpr (LINES) {
     static_assert(W == 1 && TM <= NT, "one output node per lane");
     if (tid < TL) {
-      const BatchSlot sl =
-          near ? batch_slot_near(bt, tid) : batch_slot(b, bt.p0, bt.p1, G, i0 + tid);
+      BatchSlot sl;
+      if (near)
+        sl = batch_slot_near(bt, tid);
+      else if constexpr (BATCH)
+        sl = batch_slot(b, bt.p0, bt.p1, G, i0 + tid);
+      else
+        sl = line_slot(i0 + tid, N, g.lines, G, g.inv_line);
       if (sl.j >= 0 && sl.j < sl.n) {
         onode = sl.o + sl.j;
         oprob = sl.p;
@@ -303,12 +316,14 @@ __global__ void __launch_bounds__(256)
   for (int q = tid; q < TL * W; q += NT) {
     const int t = q >> LW, c = q & (W - 1);
     int64_t i = i0 + t;
-    if constexpr (BATCH) {
+    if constexpr (LINES) {
       // q == tid here (one output node per lane)
       if (onode < 0) continue;  // a ghost slot
-      dt = odt;
-      if (mode == MODE_STAGE && dt == 0.0) continue;  // finished problem
-      ih = oih;
+      if constexpr (BATCH) {
+        dt = odt;
+        if (mode == MODE_STAGE && dt == 0.0) continue;  // finished problem
+        ih = oih;
+      }
       base = onode;
       i = 0;
     } else {
@@ -401,6 +416,14 @@ static TileGeom make_geom(int dir, const int64_t n[3], int diff, int tm, int w) 
   g.xgroups = dir == 0 ? 1 : ceil_div64(n[0], w);
   const int64_t others = dir == 0 ? n[1] * n[2] : (dir == 1 ? n[2] : n[1]);
   g.ntiles = g.segs * g.xgroups * others;
+  g.lines = 0;
+  g.inv_line = 0.0;
+  if (dir == 0) {  // packed x-lines
+    const int64_t L = n[0] + 2 * (diff ? 5 : 4);
+    g.lines = others;
+    g.inv_line = 1.0 / (double)L;
+    g.ntiles = ceil_div64(others * L, g.tl);
+  }
   return g;
 }
 
@@ -432,6 +455,8 @@ hipError_t launch_batch_sweep(const SweepArgs& a, const BatchArgs& b, int mode, 
   g.segs = 1;
   g.xgroups = 1;
   g.ntiles = b.ntiles;
+  g.lines = 0;
+  g.inv_line = 0.0;
   return sweep_shape<3, 0, true>(a, b, g, mode, stream);
 }
 

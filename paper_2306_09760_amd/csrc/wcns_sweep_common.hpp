@@ -80,6 +80,46 @@ __device__ __forceinline__ BatchSlot batch_slot_near(const BatchTile& t, int r) 
   return BatchSlot{s ? t.o1 : t.o0, s ? t.n1 : t.n0, r + (s ? t.c1 : t.c0), t.p0 + (int)s};
 }
 
+// The line holding slot v >= 0 of x-lines packed with L slots each (the
+// quotient from the double reciprocal is off by at most one below 2^52).
+__device__ __forceinline__ int64_t line_of(int64_t v, int64_t L, double invL) {
+  int64_t q = (int64_t)((double)v * invL);
+  if (q * L > v) --q;
+  if ((q + 1) * L <= v) ++q;
+  return q;
+}
+// Slot v of the packed x-lines (lines of N nodes) as a BatchSlot; slots
+// before the first line or after the last come out with j < -G or j >= N + G.
+__device__ __forceinline__ BatchSlot line_slot(int64_t v, int64_t N, int64_t lines, int G,
+                                               double invL) {
+  const int64_t L = N + 2 * G;
+  int64_t p = v < 0 ? 0 : line_of(v, L, invL);
+  if (p > lines - 1) p = lines - 1;
+  return BatchSlot{p * N, (int)N, (int)(v - p * L - G), (int)p};
+}
+// The tile of packed x-lines whose output slots start at i0 (as batch_tile).
+__device__ __forceinline__ BatchTile line_tile(int64_t i0, int64_t N, int64_t lines, int G,
+                                               int TL, double invL) {
+  const int64_t L = N + 2 * G;
+  const BatchSlot a = line_slot(i0 - G, N, lines, G, invL);
+  const BatchSlot e = line_slot(i0 + TL + G - 1, N, lines, G, invL);
+  BatchTile t;
+  t.p0 = a.p;
+  t.p1 = e.p;
+  t.o0 = a.o;
+  t.o1 = a.o + N;
+  t.n0 = t.n1 = (int)N;
+  t.c0 = a.j + G;  // node index of slot i0 (a is slot i0 - G)
+  if (t.p1 > t.p0) {
+    t.r1 = (int)((int64_t)(t.p0 + 1) * L - i0);
+    t.c1 = -t.r1 - G;
+  } else {
+    t.r1 = 1 << 30;
+    t.c1 = t.c0;
+  }
+  return t;
+}
+
 // bc_index for a node index within [-G, n + G) of a problem of n > G nodes
 __device__ __forceinline__ int bc_index_near(int j, int n, int bc) {
   if (bc == 0) return j < 0 ? j + n : (j >= n ? j - n : j);

@@ -74,6 +74,27 @@ def test_xsweep_tile_shape_invariance(lib, W, tm, diff):
     assert np.array_equal(to_host(G.residual(Ud)), ref)
 
 
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("diff", ["mnd6", "md6"])
+def test_xsweep_packed_lines_2d(lib, ora, W, bc, diff):
+    """x-lines of 300 nodes packed end to end: a tile holds the end of one
+    line, the ghosts of both and the start of the next.  Both x tile sizes
+    match the oracle and each other bitwise."""
+    prob, U = W.random_smooth_state(7, 2, (300, 24), amp=0.3)
+    U = U.copy()
+    U[0, :, 290:] *= 1.8  # a jump next to the line ends
+    prob["bc"] = (bc, "transmissive")
+    say("packed x-lines", bc, diff)
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0, diff=diff)
+    Ud = to_dev(U)
+    G.tiles = (128, 32, 4)
+    r128 = to_host(G.residual(Ud))
+    G.tiles = (256, 32, 4)
+    r256 = to_host(G.residual(Ud))
+    assert np.array_equal(r128, r256)
+    _check(r256, O.residual(U), what="packed x-lines")
+
+
 # ------------------------------------------------------------------------ 2D --
 @pytest.mark.parametrize("weights,xi", SHOCK_WEIGHTS)
 @pytest.mark.parametrize("diff", ["mnd6", "md6"])
