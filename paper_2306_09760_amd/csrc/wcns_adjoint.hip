@@ -88,16 +88,23 @@ __global__ void __launch_bounds__(256)
 
   const int64_t tile = blockIdx.x;
   if (tile >= g.ntiles) return;
-  int64_t base, N, stride;
+  // Along x the lines are packed end to end with 5 ghost slots on each side
+  // (TileGeom::lines, L = n[0] + 10): every position a node's cotangent
+  // gathers from (nodes j-5 .. j+5) then lies in its own line's slots.
+  constexpr int P = 5;
+  int64_t base = 0, N, stride = 1, i0;
   int ncol = 1;
-  const int64_t seg = tile % g.segs;
-  const int64_t r = tile / g.segs;
-  const int64_t i0 = seg * TL;
+  BatchTile bt{};
+  bool near = true;  // the tile spans at most two lines
   if constexpr (DIR == 0) {
     N = a.n[0];
-    base = r * N;
-    stride = 1;
+    i0 = tile * TL;
+    bt = line_tile(i0, N, g.lines, P, TL, g.inv_line);
+    near = bt.p1 <= bt.p0 + 1;
   } else {
+    const int64_t seg = tile % g.segs;
+    const int64_t r = tile / g.segs;
+    i0 = seg * TL;
     const int64_t xg = r % g.xgroups;
     const int64_t other = r / g.xgroups;
     const int64_t x0 = xg * W;
@@ -129,12 +136,27 @@ __global__ void __launch_bounds__(256)
     if (idx < SV) {
       const int k = idx >> LW, c = idx & (W - 1);
       const int cc = c < ncol ? c : ncol - 1;
-      const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+      if constexpr (DIR == 0) {
+        const BatchSlot sl =
+            near ? batch_slot_near(bt, k - P) : line_slot(nb + k, N, g.lines, P, g.inv_line);
+        // slots before the first line or after the last load a ghost (no
+        // node gathers from them)
+        const int j = sl.j < -P ? -P : (sl.j >= sl.n + P ? sl.n + P - 1 : sl.j);
+        const int64_t gi = sl.o + bc_index_near(j, sl.n, a.bc);
+        const bool ghost = j < 0 || j >= sl.n;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
+        for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        rbuf[it][v] = rbar_at(a.Rbar + v * a.npts, base + cc, stride, nb + k, N, a.bc);
+        for (int v = 0; v < NV; ++v)  // Rbar: zero at a transmissive ghost
+          rbuf[it][v] = (ghost && a.bc != 0) ? 0.0 : a.Rbar[v * a.npts + gi];
+      } else {
+        const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          rbuf[it][v] = rbar_at(a.Rbar + v * a.npts, base + cc, stride, nb + k, N, a.bc);
+      }
     }
   }
   double xv = 0.0;
@@ -361,11 +383,28 @@ __global__ void __launch_bounds__(256)
 
   // gather per node
   const int G = a.diff ? 5 : 4;
+  if constexpr (DIR == 0) {
+    // The line mapping is recomputed here rather than kept from the load
+    // phase: held in scalar registers through the VJP phases it would be
+    // spilled (the empty asm hides that the slot is the same, so the two
+    // computations are not merged).
+    int64_t i0r = i0;
+    asm volatile("" : "+s"(i0r));
+    bt = line_tile(i0r, N, g.lines, P, TL, g.inv_line);
+    near = bt.p1 <= bt.p0 + 1;
+  }
 #pragma unroll 1
   for (int q = tid; q < TL * W; q += NT) {
     const int t = q >> LW, c = q & (W - 1);
-    const int64_t i = i0 + t;
-    if (i >= N || c >= ncol) continue;
+    int64_t i = i0 + t;
+    if constexpr (DIR == 0) {
+      const BatchSlot sl = near ? batch_slot_near(bt, t) : line_slot(i, N, g.lines, P, g.inv_line);
+      if (sl.j < 0 || sl.j >= sl.n) continue;  // a ghost slot
+      base = sl.o;
+      i = sl.j;
+    } else {
+      if (i >= N || c >= ncol) continue;
+    }
     const int k = t + 5;  // LDS node index of node i
     double acc[NV];
 #pragma unroll
@@ -452,6 +491,14 @@ static hipError_t adj_go(const AdjArgs& a, hipStream_t s) {
   g.xgroups = DIR == 0 ? 1 : ceil_div64(a.n[0], W);
   const int64_t others = DIR == 0 ? a.n[1] * a.n[2] : (DIR == 1 ? a.n[2] : a.n[1]);
   g.ntiles = g.segs * g.xgroups * others;
+  g.lines = 0;
+  g.inv_line = 0.0;
+  if (DIR == 0) {  // packed x-lines, 5 ghost slots per side
+    const int64_t L = a.n[0] + 10;
+    g.lines = others;
+    g.inv_line = 1.0 / (double)L;
+    g.ntiles = ceil_div64(others * L, g.tl);
+  }
   if (g.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
   const size_t lds = sizeof(double) * L::lds_doubles;
   if (spec_of(a.ip) == SPEC_FE)
