@@ -86,8 +86,8 @@ __global__ void __launch_bounds__(256)
   constexpr bool TAB = SPEC == SPEC_FE;
   const int tid = threadIdx.x;
 
-  const int64_t tile = blockIdx.x;
-  if (tile >= g.ntiles) return;
+  if ((int64_t)blockIdx.x >= g.ntiles) return;
+  const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
   // Along x the lines are packed end to end with 5 ghost slots on each side
   // (TileGeom::lines, L = n[0] + 10): every position a node's cotangent
   // gathers from (nodes j-5 .. j+5) then lies in its own line's slots.
@@ -102,11 +102,12 @@ __global__ void __launch_bounds__(256)
     bt = line_tile(i0, N, g.lines, P, TL, g.inv_line);
     near = bt.p1 <= bt.p0 + 1;
   } else {
-    const int64_t seg = tile % g.segs;
-    const int64_t r = tile / g.segs;
+    // column groups fastest: adjacent groups split the same cache lines
+    const int64_t xg = tile % g.xgroups;
+    const int64_t r = tile / g.xgroups;
+    const int64_t seg = r % g.segs;
+    const int64_t other = r / g.segs;
     i0 = seg * TL;
-    const int64_t xg = r % g.xgroups;
-    const int64_t other = r / g.xgroups;
     const int64_t x0 = xg * W;
     ncol = (int)((a.n[0] - x0) < W ? (a.n[0] - x0) : W);
     if constexpr (DIR == 1) {

@@ -73,8 +73,8 @@ __global__ void __launch_bounds__(256)
   const int G = a.diff ? 5 : 4;
   const int TL = TM - (a.diff ? 5 : 3);
 
-  const int64_t tile = blockIdx.x;
-  if (tile >= g.ntiles) return;
+  if ((int64_t)blockIdx.x >= g.ntiles) return;
+  const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
   int64_t base = 0, N = 0, stride = 1, i0;
   int ncol = 1;
   double ih = a.ih, dt = 0.0;
@@ -99,11 +99,12 @@ __global__ void __launch_bounds__(256)
     near = bt.p1 <= bt.p0 + 1;
     if (mode >= MODE_STAGE) dt = *a.dt;
   } else {
-    const int64_t seg = tile % g.segs;
-    const int64_t r = tile / g.segs;
+    // column groups fastest: adjacent groups split the same cache lines
+    const int64_t xg = tile % g.xgroups;
+    const int64_t r = tile / g.xgroups;
+    const int64_t seg = r % g.segs;
+    const int64_t other = r / g.segs;
     i0 = seg * TL;
-    const int64_t xg = r % g.xgroups;
-    const int64_t other = r / g.xgroups;
     const int64_t x0 = xg * W;
     ncol = (int)((a.n[0] - x0) < W ? (a.n[0] - x0) : W);
     if constexpr (DIR == 1) {

@@ -21,6 +21,17 @@ __device__ __forceinline__ int64_t bc_index(int64_t j, int64_t N, int bc) {
   return j < 0 ? 0 : (j >= N ? N - 1 : j);  // transmissive: zeroth-order copy
 }
 
+// Logical tile of workgroup b among nt: workgroups are dealt to the 8 XCDs
+// in turn (b % 8), each with its own L2, so XCD x is given the contiguous
+// logical range [x q + min(x, r), ...) (q = nt / 8, r = nt % 8) in launch
+// order.  Neighbouring logical tiles, which share cache lines (halos, and
+// the 128-byte lines that adjacent column groups of a y or z sweep split),
+// then run on the same XCD at about the same time.  A bijection of [0, nt).
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nt) {
+  const int64_t q = nt >> 3, r = nt & 7, x = b & 7, y = b >> 3;
+  return x * q + (x < r ? x : r) + y;
+}
+
 // Slot v of a packed batch (BatchArgs) as problem p, its first node o in the
 // state arrays, its length n and the node index j = v - s_p - G (negative or
 // >= n for a ghost slot).  p0 .. p1 bound the problems the caller's slots

@@ -52,20 +52,21 @@ __global__ void __launch_bounds__(256) weno_sweep_kernel(SweepArgs a, TileGeom g
   double* sX = sW + 2 * NV * TMW;  // kExp2Tab64
   const int tid = threadIdx.x;
 
-  const int64_t tile = blockIdx.x;
-  if (tile >= g.ntiles) return;
+  if ((int64_t)blockIdx.x >= g.ntiles) return;
+  const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
   int64_t base, N, stride;
   int ncol = 1;
-  const int64_t seg = tile % g.segs;
-  const int64_t r = tile / g.segs;
+  // column groups fastest: adjacent groups split the same cache lines
+  const int64_t xg = tile % g.xgroups;
+  const int64_t r = tile / g.xgroups;
+  const int64_t seg = r % g.segs;
+  const int64_t other = r / g.segs;
   const int64_t i0 = seg * TL;
   if constexpr (DIR == 0) {
     N = a.n[0];
-    base = r * N;
+    base = other * N;
     stride = 1;
   } else {
-    const int64_t xg = r % g.xgroups;
-    const int64_t other = r / g.xgroups;
     const int64_t x0 = xg * W;
     ncol = (int)((a.n[0] - x0) < W ? (a.n[0] - x0) : W);
     if constexpr (DIR == 1) {
