@@ -49,7 +49,42 @@ def parse():
                          "(keeps profiled runs, where timings shift, on one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--sweeps-2d", action="store_true",
+                    help="only time the 2D 1024^2 residual (x and y sweeps, fixed tiles) and "
+                         "its adjoint, a few launches each (for profiler counter runs)")
     return ap.parse_args()
+
+
+def sweeps_2d(seed):
+    """The 2D periodic 1024^2 residual with x tile 256 and y tile (64, 4) and
+    its adjoint: one warm-up launch each, then 3 + 2 launches timed with HIP
+    events."""
+    import torch
+    from paper_2306_09760_amd import workloads as W
+    from paper_2306_09760_amd.solver import Plan
+    dev = torch.device("cuda")
+    prob, U_host, _ = W.adjoint2d(seed=seed, n=1024, flow_amp=0.05)
+    P = Plan(**prob, weights="fe", xi=100.0)
+    U = torch.from_numpy(U_host).to(dev)
+    P.tiles = (256, 64, 4)
+    R, Rb, Ub = torch.empty_like(U), torch.ones_like(U), torch.zeros_like(U)
+
+    def timed(fn, n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    timed(lambda: P.residual(U, R), 1)  # warm-up
+    timed(lambda: P.residual_adjoint(U, Rb, Ub), 1)
+    res_ms = timed(lambda: P.residual(U, R), 3)
+    adj_ms = timed(lambda: P.residual_adjoint(U, Rb, Ub), 2)
+    print(json.dumps({"workload": "2D Euler periodic 1024^2, FE xi=100, tiles (256, 64, 4)",
+                      "residual_ms": round(res_ms, 4), "residual_adjoint_ms": round(adj_ms, 4),
+                      "state_bytes": int(U.numel() * 8)}), flush=True)
 
 
 def source_digest():
@@ -154,6 +189,10 @@ def main():
         print("bench.py measures one GPU: the residual path has no multi-GPU form in this "
               "library (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.sweeps_2d:
+        sweeps_2d(args.seed)
+        return
 
     proto = dict(weights=args.weights, xi=args.xi, kappa=0.5, zpow=2, eps=1e-40, diff="mnd6",
                  charproj=True, gamma=1.4, bc="transmissive")
