@@ -5,9 +5,14 @@ Workload: a batch of 4096 independent 1D Euler shock tubes (gamma = 1.4),
 N_p uniform in [256, 4096] (seed 0: 8.97 M points in total), left/right
 (rho, u, p) drawn from the seed, transmissive ends, FE weights (xi = 100,
 kappa = 0.5, p = 2, eps = 1e-40), characteristic projection, MND6, SSP-RK3
-at CFL 0.5 with a per-problem dt.  One "step" is one graph-replayed SSP-RK3
-step of every problem (per-problem CFL kernel + three persistent stage
-kernels); states are resident in HBM before timing starts.
+at CFL 0.5 with a per-problem dt.  One "step" is one SSP-RK3 step of every
+problem: the per-problem dt from the CFL bound of the step's state, then the
+three stage kernels.  The K timed steps are one wcns_batch_rk3_steps call,
+in which the last stage of each step also takes the per-problem maximum
+wave rate of the state it writes (the next step's dt), so only the first
+step reads the state for its CFL bound; --single-steps times K
+graph-replayed wcns_batch_rk3_step calls instead (a CFL pass over the state
+in every step).  States are resident in HBM before timing starts.
 
 Prints one JSON line with the metric (grid-point RK3-stage updates per
 second), the roofline of the dominant kernel (the batch stage kernel) and
@@ -39,7 +44,11 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--weights", default="fe")
     ap.add_argument("--xi", type=float, default=100.0)
-    ap.add_argument("--no-graph", action="store_true", help="launch the step eagerly")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="with --single-steps: launch each step eagerly")
+    ap.add_argument("--single-steps", action="store_true",
+                    help="time K wcns_batch_rk3_step calls (CFL pass per step) instead of one "
+                         "wcns_batch_rk3_steps call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
@@ -221,20 +230,25 @@ def main():
         U.copy_(U0)
         t.zero_()
 
+    def advance(nsteps):
+        if args.single_steps:
+            for _ in range(nsteps):
+                B.rk3_step(U, t, T_END, 0.5, status)
+        else:
+            B.rk3_steps(U, t, T_END, 0.5, nsteps, status)
+
     t = torch.zeros(B.nprob, dtype=torch.float64, device=dev)
-    for _ in range(args.warmup):
-        B.rk3_step(U, t, T_END, 0.5, status)
+    advance(args.warmup)
     reset(t)
     torch.cuda.synchronize()
 
-    # ---- timed region: K graph-replayed steps ----------------------------
+    # ---- timed region: K steps --------------------------------------------
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
-        B.rk3_step(U, t, T_END, 0.5, status)
+    advance(args.steps)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -242,7 +256,8 @@ def main():
     bad = int(status.item())
 
     # Active points per step (problems stop at t = 0.2): replay untimed with a
-    # snapshot of t before every step.
+    # snapshot of t before every step (single steps give bitwise the same
+    # times as the fused call).
     reset(t)
     active_pts = 0
     for _ in range(args.steps):
@@ -476,7 +491,10 @@ def main():
                         "[256,4096], FE weights, MND6, SSP-RK3 CFL 0.5, per-problem dt",
             "nprob": int(B.nprob), "total_points": total_pts, "seed": args.seed,
             "weights": args.weights, "xi": args.xi, "tile_midpoints": int(tile),
-            "graph": not args.no_graph, "parallelism": "single GPU",
+            "step_call": ("wcns_batch_rk3_step x K" + ("" if args.no_graph else ", graph-replayed")
+                          if args.single_steps else
+                          "wcns_batch_rk3_steps (K steps, CFL maximum fused into the last stage)"),
+            "parallelism": "single GPU",
         },
         "roofline": {
             "bound": "alu",

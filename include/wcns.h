@@ -227,6 +227,17 @@ wcns_status wcns_batch_residual(wcns_batch_plan* plan, const double* U, double* 
 wcns_status wcns_batch_rk3_step(wcns_batch_plan* plan, double* U, void* work, double* t_dev,
                                 double t_end, double cfl, int32_t* status_dev, void* stream);
 wcns_status wcns_batch_set_graph(wcns_batch_plan* plan, int32_t enable);
+/* nsteps >= 0 calls of wcns_batch_rk3_step in one (never graph-captured):
+   the same states and times bit for bit for physical states.  Each step's
+   dt_p still comes from the CFL bound on that step's starting state (the
+   time-step restriction of the scheme, Sec. 4); from the second step on,
+   the maximum wave rate of problem p is taken by the previous step's last
+   stage as it writes the state, instead of by a separate pass over U.  U
+   must not be changed by others during the call's execution.  Returns
+   WCNS_EINVAL for nsteps < 0 or the arguments wcns_batch_rk3_step rejects. */
+wcns_status wcns_batch_rk3_steps(wcns_batch_plan* plan, double* U, void* work, double* t_dev,
+                                 double t_end, double cfl, int32_t nsteps, int32_t* status_dev,
+                                 void* stream);
 
 /* The two kernels of wcns_batch_rk3_step, for callers composing their own
    step.  wcns_batch_cfl: per-problem dt_p (as above) into the workspace and

@@ -211,7 +211,7 @@ struct wcns_batch_plan {
   int grid = 0;
   int cus = 256;
   InterpParams ip;
-  size_t off_W1, off_W2, off_dtp, bytes;
+  size_t off_W1, off_W2, off_dtp, off_wmax, bytes;
   // graph-captured step
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -783,6 +783,7 @@ wcns_status wcns_batch_plan_create(const wcns_desc* proto, int64_t nprob, const 
   B->off_W1 = o; o += align256(state);
   B->off_W2 = o; o += align256(state);
   B->off_dtp = o; o += align256(sizeof(double) * nprob);
+  B->off_wmax = o; o += align256(sizeof(unsigned long long) * nprob);
   B->bytes = o;
   *plan = B;
   return WCNS_OK;
@@ -839,16 +840,27 @@ wcns_status wcns_batch_residual(wcns_batch_plan* B, const double* U, double* R, 
   return WCNS_OK;
 }
 
+// One SSP-RK3 step of the batch.  dt comes from a pass over U, or (fused_dt)
+// from the per-problem maxima that the previous step's last stage left in
+// the workspace; with keep_max this step's last stage leaves them for the
+// next step.
 static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work, double* t_dev,
-                                      double t_end, double cfl, int32_t* status, hipStream_t s) {
+                                      double t_end, double cfl, int32_t* status, hipStream_t s,
+                                      bool fused_dt = false, bool keep_max = false) {
   char* w = (char*)work;
   double* W1 = (double*)(w + B->off_W1);
   double* W2 = (double*)(w + B->off_W2);
   double* dtp = (double*)(w + B->off_dtp);
+  unsigned long long* wmax = (unsigned long long*)(w + B->off_wmax);
   SweepArgs a;
   BatchArgs b;
   batch_args(B, dtp, &a, &b);
-  WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl, s), "batch cfl launch");
+  if (fused_dt)
+    WCNS_HIP(launch_batch_dt(b, t_dev, t_end, cfl, wmax, s), "batch dt launch");
+  else
+    WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl,
+                              keep_max ? wmax : nullptr, s),
+             "batch cfl launch");
   a.status = status;
   a.U0 = U;
   const double* src[3] = {U, W1, W2};
@@ -860,7 +872,25 @@ static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work,
     a.out = dst[k];
     a.ca = ca[k];
     a.cb = cb[k];
+    a.wmax = (k == 2 && keep_max) ? wmax : nullptr;
     WCNS_HIP(launch_batch_sweep(a, b, MODE_STAGE, B->tm, s), "batch stage launch");
+  }
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_rk3_steps(wcns_batch_plan* B, double* U, void* work, double* t_dev,
+                                 double t_end, double cfl, int32_t nsteps, int32_t* status_dev,
+                                 void* stream) {
+  g_err.clear();
+  if (!B || !U || !work || !t_dev) return fail(WCNS_EINVAL, "NULL argument");
+  if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0");
+  if (!std::isfinite(t_end)) return fail(WCNS_EINVAL, "t_end must be finite");
+  if (nsteps < 0) return fail(WCNS_EINVAL, "nsteps %d < 0", nsteps);
+  hipStream_t s = (hipStream_t)stream;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    const wcns_status st =
+        batch_step_enqueue(B, U, work, t_dev, t_end, cfl, status_dev, s, k > 0, k + 1 < nsteps);
+    if (st != WCNS_OK) return st;
   }
   return WCNS_OK;
 }
@@ -911,7 +941,8 @@ wcns_status wcns_batch_cfl(wcns_batch_plan* B, const double* U, void* work, doub
   SweepArgs a;
   BatchArgs b;
   batch_args(B, (double*)((char*)work + B->off_dtp), &a, &b);
-  WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl, (hipStream_t)stream),
+  WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl, nullptr,
+                            (hipStream_t)stream),
            "batch cfl launch");
   return WCNS_OK;
 }

@@ -724,6 +724,19 @@ __device__ __forceinline__ double wave_rate(const double* U, double gamma, const
   return s;
 }
 
+// Maxima of wave rates are taken on their bit patterns as unsigned integers:
+// for non-negative doubles that is the order of the values, and a NaN (of
+// either sign) exceeds every finite rate, so it always reaches dt.  Maximum
+// over the 64 lanes of a wavefront (all lanes active).
+__device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, 64);
+    v = w > v ? w : v;
+  }
+  return v;
+}
+
 // Wave speed |u_DIR| + c of one state along DIR.
 template <int ND, int DIR>
 __device__ __forceinline__ double dir_speed(const double* U, double gamma) {

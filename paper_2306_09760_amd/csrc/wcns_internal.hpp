@@ -35,6 +35,9 @@ struct SweepArgs {
   double ih;            // 1/h along the sweep direction
   InterpParams ip;
   PhysParams pp;
+  // batch stage only, may be null: per-problem maxima (bit patterns) of the
+  // wave rate of the written state, for the next step's dt
+  unsigned long long* wmax;
 };
 
 // Ragged batch description (device arrays).
@@ -77,7 +80,10 @@ hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double ga
                       const double* ih, const double* adv, double cfl, double* partial,
                       int nblocks, double* dt_out, hipStream_t stream);
 hipError_t launch_batch_cfl(const double* U, int64_t total, const BatchArgs& b, double gamma,
-                            double* t, double t_end, double cfl, hipStream_t stream);
+                            double* t, double t_end, double cfl, unsigned long long* wmax,
+                            hipStream_t stream);
+hipError_t launch_batch_dt(const BatchArgs& b, double* t, double t_end, double cfl,
+                           unsigned long long* wmax, hipStream_t stream);
 hipError_t launch_axpy_state(double* y, const double* x, double a, int64_t n,
                              hipStream_t stream);
 hipError_t launch_lincomb(double* out, const double* x, double ax, const double* y, double ay,

@@ -73,37 +73,68 @@ __global__ void __launch_bounds__(256) cfl_final_kernel(const double* __restrict
   if (threadIdx.x == 0) dt[0] = cfl / m;
 }
 
-// One block per problem: dt_p = min(cfl / max rate, t_end - t_p) for
-// problems with t_p < t_end (0 otherwise); t_p advances by dt_p.
+// The batch maxima use wave_max_bits (wcns_device.hpp).
+// dt_p = min(cfl / m, t_end - t_p) for a problem with t_p < t_end (0
+// otherwise); t_p advances by dt_p.
+__device__ __forceinline__ void batch_dt(const BatchArgs& b, int p, double m, double* t,
+                                         double t_end, double cfl) {
+  const double tp = t[p];
+  double dt = cfl / m;
+  double tn = tp + dt;
+  if (!(dt < t_end - tp)) {
+    dt = t_end - tp;
+    tn = t_end;
+  }
+  b.dtp[p] = dt;
+  t[p] = tn;
+}
+
+// One block per problem: the maximum wave rate of its nodes, then batch_dt.
+// wmax, when given, is cleared for the fused maximum of the step's last stage.
 __global__ void __launch_bounds__(256) batch_cfl_kernel(const double* __restrict__ U,
                                                         int64_t total, BatchArgs b,
                                                         double gamma, double* __restrict__ t,
-                                                        double t_end, double cfl) {
+                                                        double t_end, double cfl,
+                                                        unsigned long long* wmax) {
+  __shared__ unsigned long long red[4];
   const int p = blockIdx.x;
-  const double tp = t[p];
-  if (!(tp < t_end)) {  // uniform: the whole block leaves
+  if (wmax && threadIdx.x == 0) wmax[p] = 0;
+  if (!(t[p] < t_end)) {  // uniform: the whole block leaves
     if (threadIdx.x == 0) b.dtp[p] = 0.0;
     return;
   }
   const int64_t o0 = b.offset[p], o1 = b.offset[p + 1];
   const double ih[1] = {b.ih[p]};
-  double m = 0.0;
+  unsigned long long m = 0;
   for (int64_t i = o0 + threadIdx.x; i < o1; i += blockDim.x) {
     double u[3] = {U[i], U[total + i], U[2 * total + i]};
-    const double r = wave_rate<1>(u, gamma, ih);
-    m = (r > m || r != r) ? r : m;
+    const unsigned long long r = __builtin_bit_cast(unsigned long long, wave_rate<1>(u, gamma, ih));
+    m = r > m ? r : m;
   }
-  m = block_max256(m);
+  m = wave_max_bits(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    double dt = cfl / m;
-    double tn = tp + dt;
-    if (!(dt < t_end - tp)) {
-      dt = t_end - tp;
-      tn = t_end;
-    }
-    b.dtp[p] = dt;
-    t[p] = tn;
+    for (int w = 1; w < 4; ++w) m = red[w] > m ? red[w] : m;  // m = red[0] here
+    batch_dt(b, p, __builtin_bit_cast(double, m), t, t_end, cfl);
   }
+}
+
+// The same dt from the maxima that the previous step's last stage took as it
+// wrote the state (sweep kernel, SweepArgs::wmax); clears them for this
+// step's.  One thread per problem.
+__global__ void __launch_bounds__(256) batch_dt_kernel(BatchArgs b, double* __restrict__ t,
+                                                       double t_end, double cfl,
+                                                       unsigned long long* __restrict__ wmax) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= b.nprob) return;
+  const double m = __builtin_bit_cast(double, wmax[p]);
+  wmax[p] = 0;
+  if (!(t[p] < t_end)) {
+    b.dtp[p] = 0.0;
+    return;
+  }
+  batch_dt(b, p, m, t, t_end, cfl);
 }
 
 // ------------------------------------------------------------ elementwise --
@@ -164,9 +195,17 @@ hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double ga
 }
 
 hipError_t launch_batch_cfl(const double* U, int64_t total, const BatchArgs& b, double gamma,
-                            double* t, double t_end, double cfl, hipStream_t stream) {
+                            double* t, double t_end, double cfl, unsigned long long* wmax,
+                            hipStream_t stream) {
   hipLaunchKernelGGL(batch_cfl_kernel, dim3(b.nprob), dim3(256), 0, stream, U, total, b, gamma,
-                     t, t_end, cfl);
+                     t, t_end, cfl, wmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_dt(const BatchArgs& b, double* t, double t_end, double cfl,
+                           unsigned long long* wmax, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_dt_kernel, dim3((unsigned)ceil_div(b.nprob, 256)), dim3(256), 0,
+                     stream, b, t, t_end, cfl, wmax);
   return hipGetLastError();
 }
 

@@ -313,6 +313,7 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
 
   // flux difference and output
+  unsigned long long rbits = 0;  // wave rate of the lane's written node (SweepArgs::wmax)
 #pragma unroll 1
   for (int q = tid; q < TL * W; q += NT) {
     const int t = q >> LW, c = q & (W - 1);
@@ -360,7 +361,38 @@ __global__ void __launch_bounds__(256)
         res[v] = -ih * d;
       }
     }
-    emit_rt<NV>(mode, a, base + i * stride + c, a.npts, res, Un, dt);
+    if constexpr (BATCH) {
+      double y[NV];
+      emit_rt<NV>(mode, a, base + i * stride + c, a.npts, res, Un, dt, y);
+      if (a.wmax && mode == MODE_STAGE) {
+        const double ihv[1] = {ih};
+        rbits = __builtin_bit_cast(unsigned long long, wave_rate<1>(y, a.pp.gamma, ihv));
+      }
+    } else {
+      emit_rt<NV>(mode, a, base + i * stride + c, a.npts, res, Un, dt);
+    }
+  }
+  // The batch's last stage of a step also takes each problem's maximum wave
+  // rate of the state it writes (uniform branch; every lane reaches it).
+  if constexpr (BATCH) {
+    if (a.wmax && mode == MODE_STAGE) {
+      if (near) {
+        // The lanes' nodes belong to p0 or p0 + 1, in order, so at most one
+        // wavefront of the tile holds both: reduce only for the problems a
+        // wavefront holds (the ballots are uniform across it).
+        const bool s1 = oprob != bt.p0;
+        if (__ballot(rbits != 0 && !s1)) {
+          const unsigned long long m0 = wave_max_bits(s1 ? 0ull : rbits);
+          if ((tid & 63) == 0) atomicMax(a.wmax + bt.p0, m0);
+        }
+        if (__ballot(rbits != 0 && s1)) {
+          const unsigned long long m1 = wave_max_bits(s1 ? rbits : 0ull);
+          if ((tid & 63) == 0) atomicMax(a.wmax + bt.p0 + 1, m1);
+        }
+      } else if (rbits) {
+        atomicMax(a.wmax + oprob, rbits);
+      }
+    }
   }
 }
 

@@ -147,14 +147,14 @@ __device__ __forceinline__ void flag_status(int32_t* status) {
 template <int NV>
 __device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gidx, int64_t vstride,
                                         const double (&res)[NV], const double (&Un)[NV],
-                                        double dt);
+                                        double dt, double* yout = nullptr);
 
 // Writes one node's result according to the sweep mode.  Un is the state
 // under the stencil at that node (needed by the stage combine).
 template <int NV, int MODE>
 __device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t vstride,
                                      const double (&res)[NV], const double (&Un)[NV],
-                                     double dt) {
+                                     double dt, double* yout = nullptr) {
   if constexpr (MODE == MODE_RES) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = res[v];
@@ -188,19 +188,23 @@ __device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t v
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = y[v];
     if (!physical<NV>(y, a.pp.gamma)) flag_status(a.status);
+    if (yout) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) yout[v] = y[v];
+    }
   }
 }
 
 template <int NV>
 __device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gidx, int64_t vstride,
                                         const double (&res)[NV], const double (&Un)[NV],
-                                        double dt) {
+                                        double dt, double* yout) {
   if (mode == MODE_RES)
     emit<NV, MODE_RES>(a, gidx, vstride, res, Un, dt);
   else if (mode == MODE_ACC)
     emit<NV, MODE_ACC>(a, gidx, vstride, res, Un, dt);
   else if (mode == MODE_STAGE)
-    emit<NV, MODE_STAGE>(a, gidx, vstride, res, Un, dt);
+    emit<NV, MODE_STAGE>(a, gidx, vstride, res, Un, dt, yout);
   else
     emit<NV, MODE_LIN>(a, gidx, vstride, res, Un, dt);
 }

@@ -240,6 +240,15 @@ class BatchPlan:
                                         float(cfl), _ptr(status), _stream()), "wcns_batch_rk3_step")
         return U
 
+    def rk3_steps(self, U, t, t_end, cfl=0.5, nsteps=1, status=None):
+        """nsteps rk3_step calls in one: each step's CFL maximum is taken by
+        the previous step's last stage (see include/wcns.h)."""
+        self._check_state(U)
+        check(lib().wcns_batch_rk3_steps(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
+                                         float(cfl), int(nsteps), _ptr(status), _stream()),
+              "wcns_batch_rk3_steps")
+        return U
+
     def cfl(self, U, t, t_end, cfl=0.5):
         """Per-problem dt into the workspace; t += dt (first kernel of a step)."""
         self._check_state(U)
@@ -271,14 +280,20 @@ class BatchPlan:
     def tile(self, value):
         check(lib().wcns_batch_set_tile(self._h, int(value)), "wcns_batch_set_tile")
 
-    def run_to_time(self, U, t_end, cfl=0.5, check_every=64, max_steps=10 ** 7, status=None):
+    def run_to_time(self, U, t_end, cfl=0.5, check_every=64, max_steps=10 ** 7, status=None,
+                    fused=True):
         """Steps every problem to t_end (host checks completion every
-        ``check_every`` steps).  Returns (t, steps issued)."""
+        ``check_every`` steps): with ``fused`` in rk3_steps calls, else one
+        rk3_step call per step (graph-replayed if set_graph).  Returns (t,
+        steps issued)."""
         t = torch.zeros(self.nprob, dtype=torch.float64, device=self.device)
         steps = 0
         while steps < max_steps:
-            for _ in range(check_every):
-                self.rk3_step(U, t, t_end, cfl, status)
+            if fused:
+                self.rk3_steps(U, t, t_end, cfl, check_every, status)
+            else:
+                for _ in range(check_every):
+                    self.rk3_step(U, t, t_end, cfl, status)
             steps += check_every
             if bool((t >= t_end).all().item()):
                 break

@@ -61,16 +61,16 @@ def test_batch_residual_short_problems(lib, ora, W, diff, bc, tile):
         assert n <= 1e-12 and pt <= 1e-10, (p, n, pt)
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_steps_to_time_match_per_problem_runs(lib, ora, W, graph):
+@pytest.mark.parametrize("graph,fused", [(False, False), (True, False), (False, True)])
+def test_batch_steps_to_time_match_per_problem_runs(lib, ora, W, graph, fused):
     prob, U, meta = _small_batch(W, seed=1, nprob=10, nmin=64, nmax=300)
     t_end = 0.05
-    say("batch run to time, graph =", graph)
+    say("batch run to time, graph =", graph, "fused =", fused)
     B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
     B.set_graph(graph)
     Ud = to_dev(U)
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
-    t, steps = B.run_to_time(Ud, t_end, cfl=0.5, check_every=16, status=status)
+    t, steps = B.run_to_time(Ud, t_end, cfl=0.5, check_every=16, status=status, fused=fused)
     assert bool((t == t_end).all().item())
     assert int(status.item()) == 0
     Ug = to_host(Ud)
@@ -102,6 +102,43 @@ def test_graph_replay_equals_eager_steps(lib, W):
         res.append(out)
     for a, b in zip(*res):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nmin,nmax,tile", [(9, 40, 128), (9, 40, 256), (200, 2000, 256), (200, 2000, 128)])
+def test_rk3_steps_equal_single_steps(lib, W, nmin, nmax, tile):
+    """rk3_steps (the CFL maximum of each step taken by the previous step's
+    last stage) gives bitwise the states and times of single rk3_step calls,
+    also while problems finish and with many problems per tile."""
+    prob, U, meta = _small_batch(W, seed=6, nprob=48, nmin=nmin, nmax=nmax)
+    say("rk3_steps vs rk3_step", nmin, nmax, tile)
+    t_end = 100.0  # even problems stay far from it over 20 steps
+    # odd problems start just before t_end (they finish in their first step),
+    # the last one at t_end (finished from the start), the rest at 0
+    t0 = np.zeros(48)
+    t0[1::2] = t_end * (1.0 - 1e-6)
+    t0[-1] = t_end
+    res = []
+    for fused in (False, True):
+        B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+        B.tile = tile
+        Ud = to_dev(U)
+        t = torch.from_numpy(t0.copy()).cuda()
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        out = []
+        for chunk in (1, 5, 14):
+            if fused:
+                B.rk3_steps(Ud, t, t_end, 0.5, chunk, status)
+            else:
+                for _ in range(chunk):
+                    B.rk3_step(Ud, t, t_end, 0.5, status)
+            out.append((to_host(Ud).copy(), t.cpu().numpy().copy()))
+        assert int(status.item()) == 0
+        res.append(out)
+    finished = res[0][-1][1] >= t_end
+    assert finished[1::2].all() and not finished[0:-1:2].any()
+    for (ua, ta), (ub, tb) in zip(*res):
+        assert np.array_equal(ta, tb)
+        assert np.array_equal(ua, ub)
 
 
 def test_finished_problems_are_untouched(lib, ora, W):
