@@ -61,6 +61,28 @@ def test_batch_residual_short_problems(lib, ora, W, diff, bc, tile):
         assert n <= 1e-12 and pt <= 1e-10, (p, n, pt)
 
 
+@pytest.mark.parametrize("n", [9, 5000])
+def test_batch_single_problem(lib, ora, W, n):
+    """A batch of one problem: of the minimum length (one tile of mostly
+    ghost slots) and of 5000 nodes (many tiles, one problem each)."""
+    prob, U, meta = W.shock_tube_batch(seed=7, nprob=1, nmin=n, nmax=n)
+    say("batch of one problem", n)
+    B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+    Ud = to_dev(U)
+    R = to_host(B.residual(Ud))
+    O = _oracle(ora, meta, 0, weights="fe", xi=100.0)
+    n_, pt = rel_err(_cols(R, meta, 0), O.residual(_cols(U, meta, 0)))
+    assert n_ <= 1e-12 and pt <= 1e-10, (n_, pt)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    B.rk3_steps(Ud, t, 1.0, 0.5, 2)
+    Uo = _cols(U, meta, 0)
+    for _ in range(2):
+        dt = O.cfl_dt(Uo, 0.5)
+        Uo, bad = O.rk3_step(Uo, dt)
+    n_, pt = rel_err(_cols(to_host(Ud), meta, 0), Uo)
+    assert n_ <= 1e-12 and pt <= 1e-12, (n_, pt)
+
+
 @pytest.mark.parametrize("graph,fused", [(False, False), (True, False), (False, True)])
 def test_batch_steps_to_time_match_per_problem_runs(lib, ora, W, graph, fused):
     prob, U, meta = _small_batch(W, seed=1, nprob=10, nmin=64, nmax=300)

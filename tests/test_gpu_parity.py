@@ -95,6 +95,23 @@ def test_xsweep_packed_lines_2d(lib, ora, W, bc, diff):
     _check(r256, O.residual(U), what="packed x-lines")
 
 
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("bc", ["periodic", "transmissive"])
+@pytest.mark.parametrize("diff", ["mnd6", "md6"])
+def test_residual_minimum_grids(lib, ora, W, ndim, bc, diff):
+    """The smallest accepted grid, 9 nodes per axis: fewer nodes than ghost
+    slots plus a tile, so every x tile spans several packed lines and every
+    y/z tile is mostly ghosts."""
+    n = (9,) * ndim
+    prob, U = W.random_smooth_state(8, ndim, n, amp=0.3)
+    U = U.copy()
+    U[0].flat[::4] *= 1.5  # jumps between neighbours
+    prob["bc"] = bc
+    say("minimum grid", ndim, bc, diff)
+    G, O = _pair(lib, ora, prob, weights="fe", xi=100.0, diff=diff)
+    _check(to_host(G.residual(to_dev(U))), O.residual(U), what="minimum grid")
+
+
 # ------------------------------------------------------------------------ 2D --
 @pytest.mark.parametrize("weights,xi", SHOCK_WEIGHTS)
 @pytest.mark.parametrize("diff", ["mnd6", "md6"])
