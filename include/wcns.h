@@ -193,7 +193,7 @@ wcns_status wcns_rk3_step_adjoint_stages(wcns_plan* plan, const double* Un, cons
 wcns_status wcns_plan_autotune(wcns_plan* plan, const double* U, void* work, void* stream);
 /* Current tile shapes: [0] midpoints per tile of the x sweep (128 or 256);
    [1], [2] midpoints along the line and adjacent x-columns per tile of the
-   y/z sweeps, one of (16,8), (32,4), (32,8), (64,4). */
+   y/z sweeps, one of (16,8), (32,4), (32,8), (64,4), (128,2), (256,1). */
 void wcns_plan_get_tiles(const wcns_plan* plan, int32_t tiles[3]);
 /* Sets tile shapes (WCNS_EINVAL if not among the candidates or if the tile
    would exceed 64 KB of LDS for this system). */

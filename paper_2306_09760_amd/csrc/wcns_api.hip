@@ -50,8 +50,8 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Tile candidates: x sweeps (and the batch) take tm midpoints per tile; y/z
 // sweeps take (tm, w) = midpoints along the line by adjacent x-columns.
 const int kTmCandidates[] = {128, 256};
-const int kYzCandidates[][2] = {{16, 8}, {32, 4}, {32, 8}, {64, 4}};
-const int kNumYz = 4;
+const int kYzCandidates[][2] = {{16, 8}, {32, 4}, {32, 8}, {64, 4}, {128, 2}, {256, 1}};
+const int kNumYz = 6;
 
 bool in_list(int v, const int* l, int n) {
   for (int i = 0; i < n; ++i)

@@ -400,11 +400,11 @@ __global__ void __launch_bounds__(256)
 static inline int64_t ceil_div64(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
 // Compiled tile shapes: x direction and batch tm in {128, 256}; y/z (tm, w)
-// in {(16, 8), (32, 4), (32, 8), (64, 4)}.
+// in {(16, 8), (32, 4), (32, 8), (64, 4), (128, 2), (256, 1)}.
 bool sweep_shape_ok(int nv, int dir, int tm, int w) {
   if (dir == 0) return w == 1 && (tm == 128 || tm == 256);
   const bool known = (tm == 16 && w == 8) || (tm == 32 && w == 4) || (tm == 32 && w == 8) ||
-                     (tm == 64 && w == 4);
+                     (tm == 64 && w == 4) || (tm == 128 && w == 2) || (tm == 256 && w == 1);
   if (!known) return false;
   const size_t nr = nv > 1 ? nv + 1 : 0;
   const size_t lds = sizeof(double) * ((size_t)nv * (tm + 5) * w + (nr + 2 * nv) * (size_t)tm * w + 64);
@@ -434,6 +434,8 @@ static hipError_t sweep_shape(const SweepArgs& a, const BatchArgs& b, const Tile
     if (g.tm == 16) return sweep_go<NV, DIR, BATCH, 16, 8>(a, b, g, mode, s);
     if (g.w == 4 && g.tm == 32) return sweep_go<NV, DIR, BATCH, 32, 4>(a, b, g, mode, s);
     if (g.tm == 32) return sweep_go<NV, DIR, BATCH, 32, 8>(a, b, g, mode, s);
+    if (g.tm == 128) return sweep_go<NV, DIR, BATCH, 128, 2>(a, b, g, mode, s);
+    if (g.tm == 256) return sweep_go<NV, DIR, BATCH, 256, 1>(a, b, g, mode, s);
     return sweep_go<NV, DIR, BATCH, 64, 4>(a, b, g, mode, s);
   }
 }

@@ -123,7 +123,7 @@ def test_residual_riemann2d(lib, ora, W, weights, xi, diff):
     _check(to_host(G.residual(to_dev(U))), O.residual(U), what="riemann2d")
 
 
-@pytest.mark.parametrize("seg,bw", [(16, 8), (32, 4), (32, 8), (64, 4)])
+@pytest.mark.parametrize("seg,bw", [(16, 8), (32, 4), (32, 8), (64, 4), (128, 2), (256, 1)])
 def test_residual_2d_rectangular_and_march_shapes(lib, ora, W, seg, bw):
     """Non-square grid, periodic in x and transmissive in y, several march
     segment / lane shapes."""
@@ -243,7 +243,7 @@ def test_autotune_keeps_results_and_picks_a_candidate(lib, ora, W):
     Ud = to_dev(U)
     tiles = G.autotune(Ud)
     assert tiles[0] in (128, 256)
-    assert (tiles[1], tiles[2]) in ((16, 8), (32, 4), (32, 8), (64, 4))
+    assert (tiles[1], tiles[2]) in ((16, 8), (32, 4), (32, 8), (64, 4), (128, 2), (256, 1))
     _check(to_host(G.residual(Ud)), O.residual(U), what="after autotune")
 
 
