@@ -1,7 +1,7 @@
 // Adjoint (vector-Jacobian product) of the WCNS-FE residual on gfx950, one
 // direction per launch: Ubar += s (dL/dU)^T Rbar, or, for the first direction
-// of a step's stage, Ubar = ca A + cb B + s (dL/dU)^T Rbar (s = scale, times
-// *dt when given; see AdjArgs).
+// of a step's stage, Ubar = ca A + cb B + cc C + s (dL/dU)^T Rbar (s = scale,
+// times *dt when given; see AdjArgs).
 //
 // A workgroup of 256 lanes owns the nodes i0 .. i0+TL-1 (TL = TM - 5) of W
 // adjacent lines and recomputes the TM midpoints i0-3 .. i0+TL+1 whose
@@ -457,6 +457,7 @@ __global__ void __launch_bounds__(256)
       if (a.A) {
         y = a.ca * a.A[e];
         if (a.B) y = __builtin_fma(a.cb, a.B[e], y);
+        if (a.C) y = __builtin_fma(a.cc, a.C[e], y);
       } else {
         y = a.Ubar[e];
       }

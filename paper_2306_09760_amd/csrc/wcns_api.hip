@@ -530,7 +530,8 @@ namespace {
 // dt_dev may be null (factor 1).
 wcns_status adjoint_into(wcns_plan* plan, const double* U, const double* Rbar, double* Ubar,
                          double scale, const double* dt_dev, const double* A, double ca,
-                         const double* B, double cb, void* stream) {
+                         const double* B, double cb, void* stream, const double* C = nullptr,
+                         double cc = 0.0) {
   for (int d = 0; d < plan->d.ndim; ++d) {
     AdjArgs a;
     std::memset(&a, 0, sizeof a);
@@ -544,6 +545,8 @@ wcns_status adjoint_into(wcns_plan* plan, const double* U, const double* Rbar, d
       a.ca = ca;
       a.B = B;
       a.cb = cb;
+      a.C = C;
+      a.cc = cc;
     }
     a.npts = plan->npts;
     for (int k = 0; k < 3; ++k) a.n[k] = plan->d.n[k];
@@ -575,9 +578,7 @@ namespace {
 wcns_status rk3_adjoint_from_stages(wcns_plan* plan, const double* Un, const double* U1,
                                     const double* U2, double* lambda, void* work,
                                     const double* dt_dev, void* stream) {
-  hipStream_t s = (hipStream_t)stream;
   char* w = (char*)work;
-  const int64_t len = plan->nv * plan->npts;
   double* l2 = (double*)(w + plan->off_A1);
   double* l1 = (double*)(w + plan->off_A2);
   wcns_status st;
@@ -591,10 +592,10 @@ wcns_status rk3_adjoint_from_stages(wcns_plan* plan, const double* Un, const dou
   if ((st = adjoint_into(plan, U1, l2, l1, 0.25, dt_dev, l2, 0.25, nullptr, 0.0, stream)) !=
       WCNS_OK)
     return st;
-  //   lambda_n so far: 1/3 lambda (stage 3) + 3/4 l2 (stage 2)
-  WCNS_HIP(launch_lincomb(lambda, lambda, 1.0 / 3.0, l2, 0.75, nullptr, 0.0, len, s), "lincomb");
-  // Stage 1: U1 = Un + dt L(Un):  lambda_n += l1 + dt J(Un)^T l1
-  return adjoint_into(plan, Un, l1, lambda, 1.0, dt_dev, lambda, 1.0, l1, 1.0, stream);
+  // Stage 1: U1 = Un + dt L(Un).  lambda_n = 1/3 lambda (stage 3) + 3/4 l2
+  // (stage 2) + l1 + dt J(Un)^T l1, in the epilogue of one launch
+  return adjoint_into(plan, Un, l1, lambda, 1.0, dt_dev, lambda, 1.0 / 3.0, l2, 0.75, stream, l1,
+                      1.0);
 }
 }  // namespace
 

@@ -99,14 +99,15 @@ struct AdjArgs {
   const double* U;      // state
   const double* Rbar;   // cotangent of the residual
   double* Ubar;         // cotangent of U (output)
-  // Ubar = ca A + cb B + s (dL/dU)^T Rbar when A is set (B optional; A or B
-  // may be Ubar itself), else Ubar += s (dL/dU)^T Rbar; s = scale * (*dt)
-  // when dt is set, else scale
+  // Ubar = ca A + cb B + cc C + s (dL/dU)^T Rbar when A is set (B and C
+  // optional; any of them may be Ubar itself), else Ubar += s (dL/dU)^T Rbar;
+  // s = scale * (*dt) when dt is set, else scale
   double scale;
   const double* dt;
   const double* A;
   const double* B;
-  double ca, cb;
+  const double* C;
+  double ca, cb, cc;
   int64_t npts;
   int64_t n[3];
   int32_t bc;
