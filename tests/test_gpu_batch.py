@@ -207,3 +207,27 @@ def test_full_config2_batch_sampled(lib, ora, W):
         U1, bad = O.rk3_step(_cols(U, meta, p), dt)
         n, pt = rel_err(_cols(Ug, meta, p), U1)
         assert n <= 1e-12 and pt <= 1e-12, ("step", p, n, pt)
+
+
+def test_full_config2_batch_rk3_steps_equal_single_steps(lib, W):
+    """The benchmark's call at full size (4096 problems, autotuned tile):
+    rk3_steps gives bitwise the states and times of single rk3_step calls;
+    single steps are checked against the oracle above."""
+    prob, U, meta = W.shock_tube_batch(seed=0)
+    say("config2 full batch, rk3_steps vs rk3_step")
+    res = []
+    for fused in (False, True):
+        B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+        Ud = to_dev(U)
+        B.autotune(Ud)
+        t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        if fused:
+            B.rk3_steps(Ud, t, 0.2, 0.5, 4, status)
+        else:
+            for _ in range(4):
+                B.rk3_step(Ud, t, 0.2, 0.5, status)
+        assert int(status.item()) == 0
+        res.append((to_host(Ud), t.cpu().numpy()))
+    assert np.array_equal(res[0][1], res[1][1])
+    assert np.array_equal(res[0][0], res[1][0])
