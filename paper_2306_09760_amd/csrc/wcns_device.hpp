@@ -37,7 +37,10 @@ enum : int { WJS = 0, WZ = 1, WFE = 2, WPFE = 3, WLIN = 4 };
 // Compile-time specialisation of the interpolation.  SPEC_FE is the paper's
 // configuration (FE weights on Z weights with p = 2, one shared exponential
 // per map); SPEC_GENERIC switches on the runtime parameters.
-enum : int { SPEC_GENERIC = 0, SPEC_FE = 1 };
+// SPEC_FE: FE weights on p = 2 Z weights with one exponential per map
+// (fast_fe); SPEC_FE_SAT: the same weights where every term takes its own
+// saturating tanh (large xi, shared_exp = 0); SPEC_GENERIC: every choice.
+enum : int { SPEC_GENERIC = 0, SPEC_FE = 1, SPEC_FE_SAT = 2 };
 
 // Uniform parameters of the interpolation, passed by value to kernels.
 struct InterpParams {
@@ -350,6 +353,21 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     const double A = n0 * e1, B = n1 * e0, C = n2 * (e0 * e1);
     const double num = __builtin_fma(e2, __builtin_fma(A, c0, B * c1), C * c2);
     return (FAM::scale * num) * rcp(__builtin_fma(e2, A + B, C));
+  }
+  if constexpr (SPEC == SPEC_FE_SAT) {
+    // Z weights (p = 2) over the common denominator as above, then each map
+    // term by term (tanh_sat: +-1 without an exponential once saturated).
+    const double tau = __builtin_fabs(b0 - b2);
+    const double t2 = tau * tau;
+    const double q0 = b0 * b0, q1 = b1 * b1, q2 = b2 * b2;
+    const double z0 = D0 * (q0 + t2) * (q1 * q2);
+    const double z1 = D1 * (q1 + t2) * (q0 * q2);
+    const double z2 = D2 * (q2 + t2) * (q0 * q1);
+    const double zi = rcp(z0 + z1 + z2);
+    const double g0 = fe_g0<SPEC_GENERIC>(z0 * zi, P), g1 = fe_g1<SPEC_GENERIC>(z1 * zi, P),
+                 g2 = fe_g2<SPEC_GENERIC>(z2 * zi, P);
+    const double ginv = rcp(g0 + g1 + g2);
+    return 0.125 * ((g0 * ginv) * c0 + (g1 * ginv) * c1 + (g2 * ginv) * c2);
   }
   double a0, a1, a2;
   if (!FE && P.weights == WJS) {

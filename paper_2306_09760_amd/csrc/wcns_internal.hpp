@@ -15,7 +15,8 @@ enum SweepMode : int { MODE_RES = 0, MODE_ACC = 1, MODE_STAGE = 2, MODE_LIN = 3 
 
 // Which compiled specialisation of the interpolation serves these parameters.
 inline int spec_of(const InterpParams& ip) {
-  return (ip.weights == WFE && ip.zpow == 2 && ip.fast_fe) ? SPEC_FE : SPEC_GENERIC;
+  if (ip.weights != WFE || ip.zpow != 2) return SPEC_GENERIC;
+  return ip.fast_fe ? SPEC_FE : (ip.shared_exp ? SPEC_GENERIC : SPEC_FE_SAT);
 }
 
 // Arguments of one directional sweep.

@@ -54,11 +54,12 @@ struct SweepLayout {
 // The FE specialisation runs at six waves per SIMD: the compiler keeps it
 // within 80 VGPRs without spilling, and the largest tile (NV = 3, 256
 // midpoints, 27.3 KB of LDS) still fits six workgroups in a CU's 160 KB.
-// The generic interpolation needs ~108 VGPRs and is left unconstrained
-// (capped at 80 it spills).
+// The generic interpolation needs ~110 VGPRs and is left unconstrained
+// (capped at 80 it spills); the saturating FE one (SPEC_FE_SAT) needs ~118
+// and runs at four.
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_FE ? 6 : 1)))
+    __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_GENERIC ? 1 : (SPEC == SPEC_FE ? 6 : 4))))
     sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g, int mode) {
   using L = SweepLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TN = L::TN, TMW = L::TMW, SV = L::SV;
@@ -415,9 +416,13 @@ template <int NV, int DIR, bool BATCH, int TM, int W>
 static hipError_t sweep_go(const SweepArgs& a, const BatchArgs& b, const TileGeom& g, int mode,
                            hipStream_t s) {
   const size_t lds = sizeof(double) * SweepLayout<NV, TM, W>::lds_doubles;
-  if (spec_of(a.ip) == SPEC_FE)
+  const int spec = spec_of(a.ip);
+  if (spec == SPEC_FE)
     hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_FE, TM, W>), dim3((unsigned)g.ntiles),
                        dim3(256), lds, s, a, b, g, mode);
+  else if (spec == SPEC_FE_SAT)
+    hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_FE_SAT, TM, W>),
+                       dim3((unsigned)g.ntiles), dim3(256), lds, s, a, b, g, mode);
   else
     hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_GENERIC, TM, W>),
                        dim3((unsigned)g.ntiles), dim3(256), lds, s, a, b, g, mode);
