@@ -19,3 +19,14 @@ def test_flops_per_point_stage_match_oracle_tally(ora, W, weights):
                     bc="transmissive")
     c = P.count_residual_ops(U)
     assert sum(c.values()) / 512 + 15 == bench.FLOPS_PER_POINT_STAGE[weights]
+
+
+@pytest.mark.parametrize("gpus", ["2", "8"])
+def test_bench_refuses_more_than_one_gpu(gpus):
+    """bench.py measures one GPU: --gpus N > 1 exits with status 2 and says
+    so, before anything touches a device."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", gpus],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout.strip()
