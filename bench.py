@@ -196,7 +196,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the residual path has no multi-GPU form in this "
-              "library (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+              "library (a grid would shard into slabs with halo exchanges, a batch by "
+              "problems); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.sweeps_2d:

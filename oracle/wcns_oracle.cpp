@@ -16,7 +16,7 @@
 // (Jacobian-vector products) of the same arithmetic, used to check the
 // hand-written adjoint of the GPU path.  T = Counted tallies the arithmetic.
 //
-// Readings of points the paper leaves open (each is listed in the design doc):
+// Readings of points the paper leaves open (the GPU path takes the same):
 //  * weights: JS per eq. 11 with (IS+eps)^2; Z per eq. 14-15 with integer
 //    exponent p (default 2); FE = the mapping of eq. 20-21 and the coefficient
 //    table of Sec. 3.1 applied to the normalised Z weights, followed by a
