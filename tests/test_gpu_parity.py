@@ -223,6 +223,27 @@ def test_riemann2d_multi_step_run(lib, ora, W):
     _check(to_host(Ud), Uo, tol=tol, ptol=ptol, what="riemann2d run")
 
 
+@pytest.mark.parametrize("case", ["tube", "riemann2d"])
+def test_multi_step_run_fe_large_xi(lib, ora, W, case):
+    """FE at xi = 1e6 (every map term through its own saturating tanh) over
+    30 CFL-limited steps: GPU vs oracle to the run bar."""
+    if case == "tube":
+        prob, U, _ = W.shock_tube(1.0, 0.75, 1.0, 0.125, -0.3, 0.1, 400)
+    else:
+        prob, U, _ = W.riemann2d(seed=1, n=48)
+    say("multi-step run, FE xi = 1e6,", case)
+    G, O = _pair(lib, ora, prob, weights="fe", xi=1e6)
+    Ud = to_dev(U)
+    for _ in range(30):
+        G.rk3_step(Ud, cfl=0.5)
+    Uo, bad = O.run_steps(U, 30, cfl=0.5)
+    assert bad == 0
+    Uf, _ = ora.Problem(**prob, weights="fe", xi=1e6, variant="fma").run_steps(U, 30, cfl=0.5)
+    tol, ptol, spread = run_tolerance(Uo, Uf)
+    say("oracle rounding-order spread", spread)
+    _check(to_host(Ud), Uo, tol=tol, ptol=ptol, what=f"{case} run, xi = 1e6")
+
+
 def test_status_word_flags_nonphysical_state(lib, W):
     prob, U, _ = W.shock_tube(1.0, 0.0, 1.0, 0.125, 0.0, 0.1, 64)
     U = U.copy()
