@@ -3,4 +3,4 @@
 TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the benchmark's
 CPU-baseline leg; the GPU product path never imports it.
 """
-from .oracle import Problem, build, eigenvectors, euler_flux, fe_map, lib  # noqa: F401
+from .oracle import Problem, build, eigenvectors, euler_flux, fe_map, lib, set_threads  # noqa: F401

@@ -32,12 +32,14 @@ FAMILIES = {"wcns": 0, "weno": 1}
 
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ into liboracle.so (no FMA contraction) and
-    liboracle_fma.so (FMA contraction)."""
+    liboracle_fma.so (FMA contraction).  OpenMP shares the lines of a 2D/3D
+    residual among threads (OMP_NUM_THREADS); each line's arithmetic is the
+    same on any thread, so results do not depend on the thread count."""
     for path, fp in ((_LIB, ["-ffp-contract=off"]), (_LIB_FMA, ["-mfma", "-ffp-contract=fast"])):
         if force or not os.path.exists(path):
             tmp = path + ".tmp"
-            subprocess.check_call(["g++", "-O2", "-std=c++17", *fp, "-fPIC", "-shared",
-                                   "-o", tmp, _SRC])
+            subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", *fp, "-fPIC",
+                                   "-shared", "-o", tmp, _SRC])
             os.replace(tmp, path)
     return _LIB
 
@@ -65,6 +67,7 @@ def lib(variant: str = "plain"):
         P = C.POINTER(C.c_double)
         D = C.POINTER(_Desc)
         L.ora_nvars.argtypes = [D]
+        L.ora_set_threads.argtypes = [C.c_int]
         L.ora_residual.argtypes = [D, P, P]
         L.ora_residual_jvp.argtypes = [D, P, P, P, P]
         L.ora_cfl_dt.argtypes = [D, P, C.c_double]
@@ -94,6 +97,8 @@ def lib(variant: str = "plain"):
         L.ora_euler_flux.argtypes = [C.c_int, C.c_int, C.c_double, P, P]
         L.ora_midpoint_flux.argtypes = [D, C.c_int, P, P]
         L.ora_count_residual_ops.argtypes = [D, P, C.POINTER(C.c_longlong)]
+        L.ora_count_interpolate_ops.argtypes = [D, P, C.POINTER(C.c_longlong)]
+        L.ora_count_midpoint_flux_ops.argtypes = [D, C.c_int, P, C.POINTER(C.c_longlong)]
         _libs[variant] = L
     return _libs[variant]
 
@@ -253,6 +258,27 @@ class Problem:
         c = (C.c_longlong * 5)()
         lib(self.variant).ora_count_residual_ops(self._ref(), _p(U), c)
         return dict(zip(("add", "mul", "div", "sqrt", "tanh"), list(c)))
+
+    def count_interpolate_ops(self, u5):
+        """Arithmetic tally of one interpolation of the stencil u5."""
+        u5 = np.ascontiguousarray(u5, dtype=np.float64)
+        c = (C.c_longlong * 5)()
+        lib(self.variant).ora_count_interpolate_ops(self._ref(), _p(u5), c)
+        return dict(zip(("add", "mul", "div", "sqrt", "tanh"), list(c)))
+
+    def count_midpoint_flux_ops(self, nodes, d=0):
+        """Arithmetic tally of one midpoint flux from six nodes (6, nv)."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        assert nodes.shape == (6, self.nv)
+        c = (C.c_longlong * 5)()
+        lib(self.variant).ora_count_midpoint_flux_ops(self._ref(), d, _p(nodes), c)
+        return dict(zip(("add", "mul", "div", "sqrt", "tanh"), list(c)))
+
+
+def set_threads(n: int) -> None:
+    """Threads sharing the lines of a 2D/3D residual (0: all processors)."""
+    for variant in ("plain", "fma"):
+        lib(variant).ora_set_threads(int(n))
 
 
 def fe_map(i, w, xi, kappa=0.5, family="wcns"):

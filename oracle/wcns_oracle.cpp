@@ -32,6 +32,8 @@
 //    (3/2, -3/10, 1/30) or eq. 3's midpoint-only operator (MD6).
 //  * time integration is the three-stage SSP Runge-Kutta scheme.
 
+#include <omp.h>
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -109,6 +111,11 @@ inline double val(Counted x) { return x.v; }
 inline Counted sqrt_(Counted a) { g_ops.sqrt++; return Counted(std::sqrt(a.v)); }
 inline Counted tanh_(Counted a) { g_ops.tanh++; return Counted(std::tanh(a.v)); }
 inline Counted abs_(Counted a) { return Counted(std::fabs(a.v)); }
+
+// Whether the lines of a residual may run on several threads: not for the
+// counting scalar, whose tally is one global.
+template <class T> constexpr bool kThreaded = true;
+template <> constexpr bool kThreaded<Counted> = false;
 
 // ------------------------------------------------------------- descriptor --
 // The oracle's own problem descriptor (filled by oracle/oracle.py).
@@ -606,14 +613,22 @@ void residual(const Desc& D, const T* U, T* R) {
     const int64_t s2 = (a2 == 0) ? 1 : (a2 == 1) ? D.n[0] : D.n[0] * D.n[1];
     const double h = D.h[d];
 
+    // The lines of one direction are independent (each writes only its own
+    // nodes of R), so they may be shared among threads: every line is
+    // computed by the same arithmetic whichever thread takes it.
+    const int64_t nlines = D.n[a1] * D.n[a2];
+#pragma omp parallel if (kThreaded<T> && nlines > 1)
+    {
     // Padded line: node j (j = -G .. N-1+G) at line[(j+G)*nv + v].
     std::vector<T> line((N + 2 * G) * nv);
     // Midpoint j+1/2 stored at fhat[(j+G)*nv + v] for j = -G+2 .. N+G-4.
     std::vector<T> fhat((N + 2 * G) * nv);
     std::vector<T> fnode((N + 2 * G) * nv);
 
-    for (int64_t i2 = 0; i2 < D.n[a2]; ++i2)
-      for (int64_t i1 = 0; i1 < D.n[a1]; ++i1) {
+#pragma omp for schedule(static)
+    for (int64_t li = 0; li < nlines; ++li) {
+      {
+        const int64_t i1 = li % D.n[a1], i2 = li / D.n[a1];
         const int64_t base = i1 * s1 + i2 * s2;
         // Ghost nodes: periodic wrap or transmissive (zeroth-order) copy.
         for (int64_t j = -G; j < N + G; ++j) {
@@ -659,6 +674,8 @@ void residual(const Desc& D, const T* U, T* R) {
             R[v * np + base + i * stride] = R[v * np + base + i * stride] - dfdx;
           }
       }
+    }
+    }  // omp parallel
   }
 }
 
@@ -827,6 +844,9 @@ extern "C" {
 
 int ora_nvars(const Desc* D) { return ora::nvars(*D); }
 
+// Threads that share the lines of a residual (0: the OpenMP default).
+void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+
 int ora_residual(const Desc* D, const double* U, double* R) {
   ora::residual(*D, U, R);
   return 0;
@@ -976,6 +996,36 @@ void ora_count_residual_ops(const Desc* D, const double* U, long long* counts) {
   for (int64_t i = 0; i < len; ++i) u[i] = ora::Counted(U[i]);
   ora::g_ops = ora::OpCount();
   ora::residual(*D, u.data(), r.data());
+  counts[0] = ora::g_ops.add;
+  counts[1] = ora::g_ops.mul;
+  counts[2] = ora::g_ops.div;
+  counts[3] = ora::g_ops.sqrt;
+  counts[4] = ora::g_ops.tanh;
+}
+
+// Arithmetic tally of one interpolation (eq. 5-15, 20-21) of the stencil u.
+void ora_count_interpolate_ops(const Desc* D, const double* u, long long* counts) {
+  ora::Counted s[5];
+  for (int k = 0; k < 5; ++k) s[k] = ora::Counted(u[k]);
+  ora::g_ops = ora::OpCount();
+  ora::interpolate(*D, s);
+  counts[0] = ora::g_ops.add;
+  counts[1] = ora::g_ops.mul;
+  counts[2] = ora::g_ops.div;
+  counts[3] = ora::g_ops.sqrt;
+  counts[4] = ora::g_ops.tanh;
+}
+
+// Arithmetic tally of one midpoint flux (direction d) from six nodes (AoS).
+void ora_count_midpoint_flux_ops(const Desc* D, int d, const double* nodes, long long* counts) {
+  const int nv = ora::nvars(*D);
+  std::vector<ora::Counted> c(6 * nv);
+  for (int k = 0; k < 6 * nv; ++k) c[k] = ora::Counted(nodes[k]);
+  const ora::Counted* st[6];
+  for (int k = 0; k < 6; ++k) st[k] = c.data() + k * nv;
+  ora::Counted F[5];
+  ora::g_ops = ora::OpCount();
+  ora::midpoint_flux(*D, d, st, F);
   counts[0] = ora::g_ops.add;
   counts[1] = ora::g_ops.mul;
   counts[2] = ora::g_ops.div;

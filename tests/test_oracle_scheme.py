@@ -341,3 +341,25 @@ def test_dual_jvp_matches_central_differences(ora, W, weights, ndim):
         return (P.residual(U + eps * V) - P.residual(U - eps * V)) / (2 * eps)
     best = min(np.abs(JV - cd(eps)).max() for eps in (1e-5, 1e-6, 1e-7, 1e-8))
     assert best < 1e-7 * np.abs(JV).max()
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_threaded_residual_equals_one_thread(ora, W, ndim):
+    """The lines of a residual may run on several threads: the values (and
+    the dual-number tangents) are bitwise those of one thread."""
+    n = (24, 20) if ndim == 2 else (12, 10, 9)
+    prob, U = W.random_smooth_state(3, ndim, n, amp=0.3)
+    U = U.copy()
+    U[0].flat[::7] *= 1.4
+    V = np.random.default_rng(1).standard_normal(U.shape)
+    P = ora.Problem(**prob, weights="fe", xi=100.0)
+    try:
+        ora.set_threads(1)
+        R1 = P.residual(U)
+        _, J1 = P.residual_jvp(U, V)
+        ora.set_threads(4)
+        R4 = P.residual(U)
+        _, J4 = P.residual_jvp(U, V)
+    finally:
+        ora.set_threads(0)
+    assert np.array_equal(R1, R4) and np.array_equal(J1, J4)
