@@ -174,14 +174,18 @@ wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double
 
 /* Reverse of one SSP-RK3 step at fixed *dt_dev: recomputes the two stage
    states from Un and replaces lambda (in: adjoint of U^{n+1}) by the
-   adjoint of U^n.  Uses `work`. */
+   adjoint of U^n.  Uses `work`.  lambda must not overlap Un or `work`
+   (WCNS_EINVAL). */
 wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lambda,
                                   void* work, const double* dt_dev, void* stream);
 
 /* wcns_rk3_step_adjoint from the stage states U1, U2 that
    wcns_rk3_step_stages wrote for the step from Un with the same *dt_dev:
    the same reverse sweep without recomputing the two stage states (two
-   residual evaluations fewer).  Uses `work`. */
+   residual evaluations fewer).  Uses `work`.  lambda must not overlap Un,
+   U1, U2 or `work`, and U1, U2 may lie in `work` only outside the two
+   cotangent buffers the reverse step keeps there (in practice: pass caller
+   arrays; WCNS_EINVAL otherwise). */
 wcns_status wcns_rk3_step_adjoint_stages(wcns_plan* plan, const double* Un, const double* U1,
                                          const double* U2, double* lambda, void* work,
                                          const double* dt_dev, void* stream);
@@ -220,7 +224,12 @@ wcns_status wcns_batch_residual(wcns_batch_plan* plan, const double* U, double* 
 
 /* One SSP-RK3 step of every problem whose time t_dev[p] < t_end, each with
    its own dt_p = min(cfl-limited step, t_end - t_dev[p]); t_dev[p] += dt_p.
-   Finished problems are left untouched.  status_dev as in wcns_rk3_step.
+   Finished problems are left untouched.  status_dev as in wcns_rk3_step;
+   a problem whose maximum wave rate is not a positive finite number (its
+   state went non-physical) is stopped where it is: dt_p = 0, t_dev[p]
+   unchanged, bit 0 of *status_dev set.  The stage kernels take only the
+   tiles of problems with dt_p > 0 (a list that the step builds in `work`
+   after computing dt_p), so finished problems cost nothing.
    With wcns_batch_set_graph(plan, 1) the step's kernels are captured into
    a HIP graph on first use (for the given pointers and scalars) and
    replayed afterwards. */
@@ -245,7 +254,8 @@ wcns_status wcns_batch_rk3_steps(wcns_batch_plan* plan, double* U, void* work, d
    every problem with dt_p > 0, out = a*U0 + b*(Uk + dt_p*L(Uk)) with
    (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3); Uk, U0 and out are batch states,
    out may alias U0 but not Uk.  dt_p is the one the last wcns_batch_cfl
-   (or wcns_batch_rk3_step) left in `work`. */
+   (or wcns_batch_rk3_step) left in `work`, and so is the list of live
+   tiles the stage takes (every tile, if the tile size changed since). */
 wcns_status wcns_batch_cfl(wcns_batch_plan* plan, const double* U, void* work, double* t_dev,
                            double t_end, double cfl, void* stream);
 wcns_status wcns_batch_stage(wcns_batch_plan* plan, int32_t stage, const double* Uk,

@@ -11,23 +11,31 @@
 //   load     the TM+5 nodes of every column into LDS, ghosts applied;
 //   roe      Roe average per midpoint;
 //   interp   forward interpolation, one task per (field, midpoint), both
-//            sides (interp5_pair);
+//            sides, with the gradient of each interpolated value with
+//            respect to its five stencil values (interp5_grad: the same
+//            intermediates give both);
 //   flux     per midpoint: flux cotangent from Rbar (transpose of the MND6 /
 //            MD6 difference), local Lax-Friedrichs VJP, back-projection VJP
 //            -> cotangents of the interpolated characteristic values and of
 //            the Roe quantities;
-//   interp^T one task per (field, midpoint): VJP of both interpolations of
-//            that field -> cotangents of the six projected stencil values;
+//   interp^T one task per (field, midpoint): the cotangents of the six
+//            projected stencil values, the two interpolations' gradients
+//            times their values' cotangents (no second evaluation of the
+//            weights);
 //   proj^T   per midpoint: projection VJP of the six stencil nodes (in place
 //            in LDS) and the Roe-average VJP onto the two centre nodes;
 //   gather   per node: the six midpoint contributions, ghost positions folded
 //            onto the boundary node (transmissive), the node-flux term of
 //            MND6, and the epilogue above.
-// LDS (doubles): sU[NV][TM+5][W] | sR[NR][TMW] | sWB[6 NV][TMW] (its first
-// 2 NV rows hold the interpolated values and their cotangents first, the
-// rest Rbar of the tile's nodes until the interpolation VJP) | the 64-entry
-// exp table, TMW = TM W.  The Roe-quantity cotangent of a midpoint
-// stays in its lane's registers from the flux VJP to the projection VJP.
+// LDS (doubles): sU[NV][TM+5][W] | sR[NR][TMW] | sWB[12 NV][TMW] | sRB[NV][TM+5][W]
+// | the 64-entry exp table, TMW = TM W.  Slot s of task (field v, midpoint
+// q) is sWB[(s NV + v) TMW + q]: slots 0, 1 hold the left and right
+// interpolated values, then their cotangents; slots 2-6 and 7-11 the two
+// gradients; the interpolation VJP overwrites slots 0-5 with the cotangents
+// of the six stencil values (each task reads its own slots first).  sRB holds
+// Rbar of the tile's nodes for the flux VJP.  The Roe-quantity cotangent of a
+// midpoint stays in its lane's registers from the flux VJP to the projection
+// VJP.
 #include <hip/hip_runtime.h>
 
 #include "wcns_adjoint_device.hpp"
@@ -45,9 +53,15 @@ struct AdjLayout {
   static constexpr int SV = TN * W;
   static constexpr int LW = W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4;
   static constexpr int LTMW = TMW == 64 ? 6 : TMW == 128 ? 7 : 8;
-  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(NR + 6 * NV) * TMW + 64;
+  static constexpr int NS = 12;  // LDS slots per (field, midpoint) task
+  static constexpr size_t lds_doubles =
+      2 * (size_t)NV * SV + (size_t)(NR + NS * NV) * TMW + 64;
   static_assert(TMW == 64 || TMW == 128 || TMW == 256, "tile must hold 64, 128 or 256 midpoints");
   static_assert((1 << LW) == W, "W must be a power of two up to 16");
+  // Workgroups (of four waves) a CU's 160 KB of LDS holds, at most four:
+  // the waves per SIMD, and so the register budget, of the instance.
+  static constexpr int per_cu = (int)((160 * 1024) / (lds_doubles * sizeof(double)));
+  static constexpr int waves = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
 };
 
 // Rbar at position j of a line (zero outside a transmissive line).
@@ -58,14 +72,10 @@ __device__ __forceinline__ double rbar_at(const double* Rb, int64_t base, int64_
   return Rb[base + j * stride];
 }
 
-#ifndef WCNS_ADJ_WAVES_PER_SIMD
-#define WCNS_ADJ_WAVES_PER_SIMD 4
-#endif
-// Register budget for WCNS_ADJ_WAVES_PER_SIMD waves per SIMD (the LDS of a
-// 128-midpoint tile allows four workgroups per CU).
+// Register budget for the waves per SIMD that the tile's LDS allows.
 template <int NV, int DIR, int SPEC, int TM, int W>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(WCNS_ADJ_WAVES_PER_SIMD)))
+    __attribute__((amdgpu_waves_per_eu(AdjLayout<NV, TM, W>::waves)))
     adj_sweep_kernel(AdjArgs a, TileGeom g) {
   using L = AdjLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TMW = L::TMW, SV = L::SV;
@@ -74,15 +84,15 @@ __global__ void __launch_bounds__(256)
   constexpr int TL = TM - 5;
   extern __shared__ double smem[];
   static_assert(TMW <= NT, "one midpoint per lane in the per-midpoint phases");
+  constexpr int NS = L::NS;
   double* sU = smem;
   double* sR = sU + NV * SV;
   double* sWB = sR + NR * TMW;
-  // Interpolated values and their cotangents (left field v in row v, right in
-  // row NV + v) share rows 0 .. 2NV-1 of sWB: the interpolation VJP task of
-  // (field v, midpoint) reads exactly its own two entries before writing
-  // stencil slots 0 and 1 of field v over them.
+  // Interpolated values and their cotangents: left field v in row v, right in
+  // row NV + v (slots 0 and 1).
   double* sW = sWB;
-  double* sX = sWB + 6 * NV * TMW;  // kExp2Tab64
+  double* sRB = sWB + NS * NV * TMW;  // Rbar of the tile's nodes
+  double* sX = sRB + NV * SV;         // kExp2Tab64
   constexpr bool TAB = SPEC == SPEC_FE;
   const int tid = threadIdx.x;
 
@@ -126,10 +136,7 @@ __global__ void __launch_bounds__(256)
   constexpr int NIT = (SV + NT - 1) / NT;
   static_assert(NIT <= 2, "a tile holds at most two nodes per lane");
   // Rbar of the same nodes (the transposed difference of the flux VJP reads
-  // nodes m-2 .. m+3 of every midpoint m) goes to sWB rows 2 NV .. 6 NV - 1,
-  // which stay unused until the interpolation VJP.
-  double* sRB = sWB + 2 * NV * TMW;
-  static_assert(NV * SV <= 4 * NV * TMW, "Rbar staging exceeds the free sWB rows");
+  // nodes m-2 .. m+3 of every midpoint m) goes to sRB.
   double buf[NIT][NV], rbuf[NIT][NV];
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
@@ -255,12 +262,19 @@ __global__ void __launch_bounds__(256)
     }
   };
 
-  // forward interpolation, one task per (field, midpoint): both sides
+  // forward interpolation, one task per (field, midpoint): both sides, each
+  // with its gradient (slots 2-6: left, over w[0..4]; 7-11: right, over
+  // w[5], w[4], .., w[1])
 #pragma unroll 1
   for (int q = tid; q < NV * TMW; q += NT) {
-    double w[6];
+    double w[6], G[5];
     stencil(q & (TMW - 1), q >> LTMW, w);
-    interp5_pair<SPEC, TAB>(a.ip, w, sW + q, sW + NV * TMW + q, sX);
+    sW[q] = interp5_grad<SPEC, TAB>(a.ip, w[0], w[1], w[2], w[3], w[4], G, sX);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) sWB[(2 + j) * NV * TMW + q] = G[j];
+    sW[NV * TMW + q] = interp5_grad<SPEC, TAB>(a.ip, w[5], w[4], w[3], w[2], w[1], G, sX);
+#pragma unroll
+    for (int j = 0; j < 5; ++j) sWB[(7 + j) * NV * TMW + q] = G[j];
   }
   __syncthreads();
 
@@ -324,22 +338,25 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
 
-  // interpolation VJP, one task per (field, midpoint): sWB[(j NV + v)] <- cotangent
-  // of stencil value j of field v
+  // interpolation VJP, one task per (field, midpoint): slot j <- cotangent
+  // of stencil value j of the field, from the task's own slots (the
+  // neighbouring tasks write the other fields' rows)
 #pragma unroll 1
   for (int q = tid; q < NV * TMW; q += NT) {
-    const int v = q >> LTMW;
-    const int rem = q & (TMW - 1);
-    double w[6], wb[6];
-    stencil(rem, v, w);
+    const double ybL = sWB[q], ybR = sWB[NV * TMW + q];
+    double GL[5], GR[5];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) wb[j] = 0.0;
-    interp5_vjp<SPEC, TAB>(a.ip, w[0], w[1], w[2], w[3], w[4], sW[v * TMW + rem], wb[0], wb[1],
-                           wb[2], wb[3], wb[4], sX);
-    interp5_vjp<SPEC, TAB>(a.ip, w[5], w[4], w[3], w[2], w[1], sW[(NV + v) * TMW + rem], wb[5],
-                           wb[4], wb[3], wb[2], wb[1], sX);
+    for (int j = 0; j < 5; ++j) {
+      GL[j] = sWB[(2 + j) * NV * TMW + q];
+      GR[j] = sWB[(7 + j) * NV * TMW + q];
+    }
+    double wb[6];
+    wb[0] = ybL * GL[0];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) sWB[(j * NV + v) * TMW + rem] = wb[j];
+    for (int j = 1; j < 5; ++j) wb[j] = __builtin_fma(ybR, GR[5 - j], ybL * GL[j]);
+    wb[5] = ybR * GR[0];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sWB[j * NV * TMW + q] = wb[j];
   }
   __syncthreads();
 
@@ -478,9 +495,12 @@ static inline int64_t ceil_div64(int64_t x, int64_t y) { return (x + y - 1) / y;
 #ifndef WCNS_ADJ_YZ_W
 #define WCNS_ADJ_YZ_W 2
 #endif
+#ifndef WCNS_ADJ_TMW4
+#define WCNS_ADJ_TMW4 64
+#endif
 template <int NV, int DIR>
 struct AdjShape {
-  static constexpr int TMW = NV == 5 ? 64 : 128;
+  static constexpr int TMW = NV == 5 ? 64 : (NV == 4 ? WCNS_ADJ_TMW4 : 128);
   static constexpr int W = DIR == 0 ? 1 : WCNS_ADJ_YZ_W;
   static constexpr int TM = TMW / W;
 };
@@ -489,7 +509,7 @@ template <int NV, int DIR>
 static hipError_t adj_go(const AdjArgs& a, hipStream_t s) {
   constexpr int TM = AdjShape<NV, DIR>::TM, W = AdjShape<NV, DIR>::W;
   using L = AdjLayout<NV, TM, W>;
-  static_assert(L::lds_doubles * sizeof(double) <= 64 * 1024, "adjoint tile exceeds 64 KB of LDS");
+  static_assert(L::lds_doubles * sizeof(double) <= 160 * 1024, "adjoint tile exceeds 160 KB of LDS");
   TileGeom g;
   g.tm = TM;
   g.w = W;

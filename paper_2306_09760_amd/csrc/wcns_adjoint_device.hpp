@@ -21,7 +21,8 @@ __device__ __forceinline__ double fe_g_d(int i, double w, const InterpParams& P,
 
 // The FE weights' part of the VJP on the forward SPEC_FE arithmetic: from
 // the indicators IS_k, the candidates c_k and the output cotangent yb, the
-// cotangents of the candidates (the weights times yb) and of the indicators.
+// cotangents of the candidates (the weights times yb) and of the indicators
+// (interp5_grad takes yb = 1: then the first three are the weights).
 // Z weights z_k = Z_k / sum Z with Z_k = d_k (q_k + tau^2) prod_{l != k} q_l,
 // q_k = (IS_k + eps)^2 (polynomial in q and tau^2, so their cotangents need
 // no reciprocal); per map, with i_j = 1 / D_j = o_j / e (o_j the product of
@@ -114,16 +115,23 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
   ISb2 -= taub * sg;
 }
 
-// Cotangent of the inputs (a, b, c, e, f) = (u_{i-2} .. u_{i+2}) of one
-// nonlinear interpolation (the left-biased one of interp5_pair) for output
-// cotangent yb; accumulates into the five references.
+// One nonlinear interpolation (the left-biased one of interp5_pair) of the
+// stencil (a, b, c, e, f) = (u_{i-2} .. u_{i+2}) and its gradient: returns
+// the interpolated value y and G[j] = dy/du_j.  The value and the gradient
+// come from the same intermediates (the weights, the maps and their slopes),
+// so the adjoint needs no second evaluation of the weights: the cotangent of
+// the stencil for an output cotangent yb is yb G.  y equals the forward
+// value of interp5_pair to rounding (the weights are normalised here map by
+// map rather than over one common denominator).
 // xt: the kExp2Tab64 table in LDS (TAB = true, FE specialisation only).
 template <int SPEC = SPEC_GENERIC, bool TAB = false>
-__device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, double b, double c,
-                                            double e, double f, double yb, double& ab, double& bb,
-                                            double& cb, double& eb, double& fb,
-                                            const double* xt = nullptr) {
+__device__ __forceinline__ double interp5_grad(const InterpParams& P, double a, double b, double c,
+                                               double e, double f, double (&G)[5],
+                                               const double* xt = nullptr) {
   constexpr bool FE = (SPEC == SPEC_FE);
+  constexpr double yb = 1.0;
+  double y;
+  double ab = 0.0, bb = 0.0, cb = 0.0, eb = 0.0, fb = 0.0;
   const double c0 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
   const double c1 = 0.125 * (-b + 6.0 * c + 3.0 * e);
   const double c2 = 0.125 * (3.0 * c + 6.0 * e - f);
@@ -132,6 +140,7 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     c0b = D0 * yb;
     c1b = D1 * yb;
     c2b = D2 * yb;
+    y = D0 * c0 + D1 * c1 + D2 * c2;
   } else {
     const double d0 = b - a, d1 = c - b, d2 = e - c, d3 = f - e;
     const double f0 = 0.5 * (3.0 * d1 - d0), s0 = d1 - d0;
@@ -143,6 +152,7 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
     double ISb0, ISb1, ISb2;
     if constexpr (FE) {
       fe_weights_vjp<TAB>(P, c0, c1, c2, IS0, IS1, IS2, yb, c0b, c1b, c2b, ISb0, ISb1, ISb2, xt);
+      y = c0b * c0 + c1b * c1 + c2b * c2;  // (the weights, yb = 1)
     } else {
       const double r0 = rcp(IS0 + P.eps), r1 = rcp(IS1 + P.eps), r2 = rcp(IS2 + P.eps);
       double a0, a1, a2, w0, w1, w2, tau = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0;
@@ -201,6 +211,7 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
       c0b = w0 * yb;
       c1b = w1 * yb;
       c2b = w2 * yb;
+      y = w0 * c0 + w1 * c1 + w2 * c2;
       // z = alpha / sum(alpha)
       const double zdot = zb0 * z0 + zb1 * z1 + zb2 * z2;
       const double ab0 = (zb0 - zdot) * inv, ab1 = (zb1 - zdot) * inv, ab2 = (zb2 - zdot) * inv;
@@ -249,6 +260,12 @@ __device__ __forceinline__ void interp5_vjp(const InterpParams& P, double a, dou
   cb += 1.875 * c0b + 0.75 * c1b + 0.375 * c2b;
   eb += 0.375 * c1b + 0.75 * c2b;
   fb += -0.125 * c2b;
+  G[0] = ab;
+  G[1] = bb;
+  G[2] = cb;
+  G[3] = eb;
+  G[4] = fb;
+  return y;
 }
 
 // Ub += (dF/dU)^T Fb + (d lam/dU)^T lamb for the Euler flux along DIR and the

@@ -211,7 +211,12 @@ struct wcns_batch_plan {
   int grid = 0;
   int cus = 256;
   InterpParams ip;
-  size_t off_W1, off_W2, off_dtp, off_wmax, bytes;
+  int64_t max_tiles = 0;  // tiles of the smallest tile candidate (sizes the live list)
+  // workspace and tile size of the last live-list rebuild (wcns_batch_stage
+  // uses the list only if both still hold)
+  const void* list_work = nullptr;
+  int list_tm = 0;
+  size_t off_W1, off_W2, off_dtp, off_wmax, off_live, off_nlive, bytes;
   // graph-captured step
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
@@ -433,18 +438,18 @@ wcns_status wcns_cfl_dt(wcns_plan* plan, const double* U, double cfl, double* dt
 }
 
 namespace {
-// One SSP-RK3 step of U in place with the stage states in W1, W2.
-wcns_status rk3_step_into(wcns_plan* plan, double* U, double* W1, double* W2, void* work,
-                          const double* dt_dev, double cfl, int32_t* status_dev, void* stream) {
+// One SSP-RK3 step of U in place with the stage states in W1, W2, the
+// residual accumulator of the 2D/3D sweeps in Racc, and (for a cfl-limited
+// step) the block maxima in partial and dt in dtw.
+wcns_status rk3_step_bufs(wcns_plan* plan, double* U, double* W1, double* W2, double* Racc,
+                          double* partial, double* dtw, const double* dt_dev, double cfl,
+                          int32_t* status_dev, void* stream) {
   hipStream_t s = (hipStream_t)stream;
-  char* w = (char*)work;
-  double* Racc = (double*)(w + plan->off_R);
   const double* dt = dt_dev;
   if (!dt) {
     if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0 when dt_dev is NULL");
-    double* dtw = (double*)(w + plan->off_dt);
     WCNS_HIP(launch_cfl(plan->nv, plan->d.ndim, U, plan->npts, plan->d.gamma, plan->ih,
-                        plan->d.adv_speed, cfl, (double*)(w + plan->off_partial), plan->ncfl, dtw, s),
+                        plan->d.adv_speed, cfl, partial, plan->ncfl, dtw, s),
              "cfl launch");
     dt = dtw;
   }
@@ -454,6 +459,16 @@ wcns_status rk3_step_into(wcns_plan* plan, double* U, double* W1, double* W2, vo
   if ((st = stage(plan, W2, U, U, 1.0 / 3.0, 2.0 / 3.0, dt, Racc, status_dev, s)) != WCNS_OK) return st;
   return WCNS_OK;
 }
+
+// rk3_step_bufs with the buffers in the caller's workspace.
+wcns_status rk3_step_into(wcns_plan* plan, double* U, double* W1, double* W2, void* work,
+                          const double* dt_dev, double cfl, int32_t* status_dev, void* stream) {
+  char* w = (char*)work;
+  return rk3_step_bufs(plan, U, W1, W2, (double*)(w + plan->off_R),
+                       (double*)(w + plan->off_partial), (double*)(w + plan->off_dt), dt_dev, cfl,
+                       status_dev, stream);
+}
+
 }  // namespace
 
 wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev, double cfl,
@@ -574,6 +589,32 @@ wcns_status wcns_residual_adjoint(wcns_plan* plan, const double* U, const double
 }
 
 namespace {
+// Arrays [p, p + bytes) and [q, q + bytes) overlap.
+bool overlaps(const void* p, size_t pb, const void* q, size_t qb) {
+  const char* a = (const char*)p;
+  const char* b = (const char*)q;
+  return a < b + qb && b < a + pb;
+}
+
+// The reverse step writes lambda in place while neighbouring tiles still read
+// the states under the stencil, and keeps its stage cotangents in the
+// workspace: lambda must not overlap Un, U1, U2 or the workspace, and the
+// states must not overlap the workspace's cotangent buffers.
+wcns_status adjoint_aliasing(const wcns_plan* P, const double* Un, const double* U1,
+                             const double* U2, const double* lambda, const void* work) {
+  const size_t sb = sizeof(double) * P->nv * P->npts;
+  const double* st[3] = {Un, U1, U2};
+  for (const double* x : st)
+    if (x && overlaps(lambda, sb, x, sb))
+      return fail(WCNS_EINVAL, "lambda must not overlap Un, U1 or U2");
+  if (overlaps(lambda, sb, work, P->bytes)) return fail(WCNS_EINVAL, "lambda must not overlap work");
+  const char* w = (const char*)work;
+  for (const double* x : st)
+    if (x && (overlaps(x, sb, w + P->off_A1, sb) || overlaps(x, sb, w + P->off_A2, sb)))
+      return fail(WCNS_EINVAL, "a state overlaps the workspace's cotangent buffers");
+  return WCNS_OK;
+}
+
 // Reverse of one SSP-RK3 step given its stage states U1, U2.
 wcns_status rk3_adjoint_from_stages(wcns_plan* plan, const double* Un, const double* U1,
                                     const double* U2, double* lambda, void* work,
@@ -605,6 +646,10 @@ wcns_status wcns_rk3_step_adjoint(wcns_plan* plan, const double* Un, double* lam
   if (!plan || !Un || !lambda || !work || !dt_dev) return fail(WCNS_EINVAL, "NULL argument");
   if (plan->d.scheme != WCNS_SCHEME_WCNS)
     return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
+  {
+    const wcns_status st = adjoint_aliasing(plan, Un, nullptr, nullptr, lambda, work);
+    if (st != WCNS_OK) return st;
+  }
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)work;
   double* U1 = (double*)(w + plan->off_W1);
@@ -626,6 +671,10 @@ wcns_status wcns_rk3_step_adjoint_stages(wcns_plan* plan, const double* Un, cons
     return fail(WCNS_EINVAL, "NULL argument");
   if (plan->d.scheme != WCNS_SCHEME_WCNS)
     return fail(WCNS_EUNSUPPORTED, "the adjoint covers the WCNS scheme");
+  {
+    const wcns_status st = adjoint_aliasing(plan, Un, U1, U2, lambda, work);
+    if (st != WCNS_OK) return st;
+  }
   return rk3_adjoint_from_stages(plan, Un, U1, U2, lambda, work, dt_dev, stream);
 }
 
@@ -727,6 +776,7 @@ static wcns_status batch_build_tiles(wcns_batch_plan* B) {
   B->d_tile_p0 = nullptr;
   B->d_tile_p1 = nullptr;
   B->ntiles = (int32_t)nt;
+  B->list_work = nullptr;
   WCNS_HIP(hipMalloc(&B->d_tile_p0, sizeof(int32_t) * tp.size()), "hipMalloc tiles");
   WCNS_HIP(hipMalloc(&B->d_tile_p1, sizeof(int32_t) * tq.size()), "hipMalloc tiles");
   WCNS_HIP(hipMemcpy(B->d_tile_p0, tp.data(), sizeof(int32_t) * tp.size(), hipMemcpyHostToDevice), "copy tiles");
@@ -779,12 +829,23 @@ wcns_status wcns_batch_plan_create(const wcns_desc* proto, int64_t nprob, const 
   if ((e = hipMemcpy(B->d_ih, B->h_ih.data(), sizeof(double) * nprob, hipMemcpyHostToDevice)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMemcpy"));
   if ((st = batch_build_tiles(B)) != WCNS_OK) return cleanup(st);
+  {
+    // the most tiles any candidate shape needs (the smallest tile)
+    const int G = proto->diff ? 5 : 4;
+    const int64_t V = B->h_offset[nprob] + 2 * G * nprob;
+    for (int tm : kTmCandidates) {
+      const int TL = tm - (proto->diff ? 5 : 3);
+      B->max_tiles = std::max(B->max_tiles, (V + TL - 1) / TL);
+    }
+  }
   const size_t state = sizeof(double) * 3 * B->total;
   size_t o = 0;
   B->off_W1 = o; o += align256(state);
   B->off_W2 = o; o += align256(state);
   B->off_dtp = o; o += align256(sizeof(double) * nprob);
   B->off_wmax = o; o += align256(sizeof(unsigned long long) * nprob);
+  B->off_live = o; o += align256(sizeof(int32_t) * B->max_tiles);
+  B->off_nlive = o; o += 256;
   B->bytes = o;
   *plan = B;
   return WCNS_OK;
@@ -805,7 +866,8 @@ wcns_status wcns_batch_plan_destroy(wcns_batch_plan* B) {
 int64_t wcns_batch_state_elems(const wcns_batch_plan* B) { return B ? 3 * B->total : 0; }
 size_t wcns_batch_workspace_bytes(const wcns_batch_plan* B) { return B ? B->bytes : 0; }
 
-static void batch_args(const wcns_batch_plan* B, double* dtp, SweepArgs* a, BatchArgs* b) {
+static void batch_args(const wcns_batch_plan* B, double* dtp, SweepArgs* a, BatchArgs* b,
+                       void* work = nullptr) {
   std::memset(a, 0, sizeof *a);
   std::memset(b, 0, sizeof *b);
   a->npts = B->total;
@@ -825,6 +887,20 @@ static void batch_args(const wcns_batch_plan* B, double* dtp, SweepArgs* a, Batc
   b->tile_p1 = B->d_tile_p1;
   b->ntiles = B->ntiles;
   b->nprob = (int32_t)B->nprob;
+  // stage launches walk the live-tile list in the workspace
+  b->live = work ? (const int32_t*)((const char*)work + B->off_live) : nullptr;
+  b->nlive = work ? (const int32_t*)((const char*)work + B->off_nlive) : nullptr;
+}
+
+// The live-tile list of the dt just computed (the dt kernel cleared the count).
+static wcns_status batch_rebuild_live(wcns_batch_plan* B, const BatchArgs& b, void* work,
+                                      hipStream_t s) {
+  char* w = (char*)work;
+  B->list_work = work;
+  B->list_tm = B->tm;
+  WCNS_HIP(launch_batch_live(b, (int32_t*)(w + B->off_live), (int32_t*)(w + B->off_nlive), s),
+           "batch live-list launch");
+  return WCNS_OK;
 }
 
 wcns_status wcns_batch_residual(wcns_batch_plan* B, const double* U, double* R, void* work, void* stream) {
@@ -844,24 +920,32 @@ wcns_status wcns_batch_residual(wcns_batch_plan* B, const double* U, double* R, 
 // One SSP-RK3 step of the batch.  dt comes from a pass over U, or (fused_dt)
 // from the per-problem maxima that the previous step's last stage left in
 // the workspace; with keep_max this step's last stage leaves them for the
-// next step.
+// next step.  With rebuild the live-tile list is rebuilt from this step's
+// dt; otherwise the list of an earlier step of the same call is used (a
+// superset: problems only finish).
 static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work, double* t_dev,
                                       double t_end, double cfl, int32_t* status, hipStream_t s,
-                                      bool fused_dt = false, bool keep_max = false) {
+                                      bool fused_dt = false, bool keep_max = false,
+                                      bool rebuild = true) {
   char* w = (char*)work;
   double* W1 = (double*)(w + B->off_W1);
   double* W2 = (double*)(w + B->off_W2);
   double* dtp = (double*)(w + B->off_dtp);
   unsigned long long* wmax = (unsigned long long*)(w + B->off_wmax);
+  int32_t* nlive = rebuild ? (int32_t*)(w + B->off_nlive) : nullptr;
   SweepArgs a;
   BatchArgs b;
-  batch_args(B, dtp, &a, &b);
+  batch_args(B, dtp, &a, &b, work);
   if (fused_dt)
-    WCNS_HIP(launch_batch_dt(b, t_dev, t_end, cfl, wmax, s), "batch dt launch");
+    WCNS_HIP(launch_batch_dt(b, t_dev, t_end, cfl, wmax, status, nlive, s), "batch dt launch");
   else
     WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl,
-                              keep_max ? wmax : nullptr, s),
+                              keep_max ? wmax : nullptr, status, nlive, s),
              "batch cfl launch");
+  if (rebuild) {
+    const wcns_status st = batch_rebuild_live(B, b, work, s);
+    if (st != WCNS_OK) return st;
+  }
   a.status = status;
   a.U0 = U;
   const double* src[3] = {U, W1, W2};
@@ -879,6 +963,11 @@ static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work,
   return WCNS_OK;
 }
 
+// Within one wcns_batch_rk3_steps call the live-tile list is rebuilt every
+// kLiveEvery steps (and for the first); in between, tiles whose problems
+// finished stay listed and leave at once.
+static const int32_t kLiveEvery = 4;
+
 wcns_status wcns_batch_rk3_steps(wcns_batch_plan* B, double* U, void* work, double* t_dev,
                                  double t_end, double cfl, int32_t nsteps, int32_t* status_dev,
                                  void* stream) {
@@ -889,8 +978,8 @@ wcns_status wcns_batch_rk3_steps(wcns_batch_plan* B, double* U, void* work, doub
   if (nsteps < 0) return fail(WCNS_EINVAL, "nsteps %d < 0", nsteps);
   hipStream_t s = (hipStream_t)stream;
   for (int32_t k = 0; k < nsteps; ++k) {
-    const wcns_status st =
-        batch_step_enqueue(B, U, work, t_dev, t_end, cfl, status_dev, s, k > 0, k + 1 < nsteps);
+    const wcns_status st = batch_step_enqueue(B, U, work, t_dev, t_end, cfl, status_dev, s, k > 0,
+                                              k + 1 < nsteps, k % kLiveEvery == 0);
     if (st != WCNS_OK) return st;
   }
   return WCNS_OK;
@@ -941,11 +1030,11 @@ wcns_status wcns_batch_cfl(wcns_batch_plan* B, const double* U, void* work, doub
   if (!std::isfinite(t_end)) return fail(WCNS_EINVAL, "t_end must be finite");
   SweepArgs a;
   BatchArgs b;
-  batch_args(B, (double*)((char*)work + B->off_dtp), &a, &b);
-  WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl, nullptr,
-                            (hipStream_t)stream),
+  batch_args(B, (double*)((char*)work + B->off_dtp), &a, &b, work);
+  WCNS_HIP(launch_batch_cfl(U, B->total, b, B->d.gamma, t_dev, t_end, cfl, nullptr, nullptr,
+                            (int32_t*)((char*)work + B->off_nlive), (hipStream_t)stream),
            "batch cfl launch");
-  return WCNS_OK;
+  return batch_rebuild_live(B, b, work, (hipStream_t)stream);
 }
 
 wcns_status wcns_batch_stage(wcns_batch_plan* B, int32_t stage, const double* Uk, const double* U0,
@@ -958,7 +1047,10 @@ wcns_status wcns_batch_stage(wcns_batch_plan* B, int32_t stage, const double* Uk
   const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
   SweepArgs a;
   BatchArgs b;
-  batch_args(B, (double*)((char*)work + B->off_dtp), &a, &b);
+  // the live list of the last wcns_batch_cfl on this workspace and tiling,
+  // else every tile
+  const bool list = B->list_work == work && B->list_tm == B->tm;
+  batch_args(B, (double*)((char*)work + B->off_dtp), &a, &b, list ? work : nullptr);
   a.status = status_dev;
   a.U = Uk;
   a.U0 = U0;

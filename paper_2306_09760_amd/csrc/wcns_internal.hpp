@@ -46,12 +46,17 @@ struct SweepArgs {
 // of a virtual index space, s_p = offset[p] + 2 G p (G ghost slots on each
 // side of its nodes), and tile k outputs the slots [k TL, k TL + TL), so a
 // tile may span the end of one problem and the start of the next.
+// Stage launches may walk a list of live tiles instead of every tile: a
+// persistent grid (resident workgroups only) takes the list positions, each
+// XCD a contiguous range of them.
 struct BatchArgs {
   const int64_t* offset;   // nprob+1 column offsets
   const double* ih;        // 1/h per problem
   double* dtp;             // per-problem dt of the current step (0 = inactive)
   const int32_t* tile_p0;  // first and last problem that the slots a tile
   const int32_t* tile_p1;  //   loads (outputs and halo) touch
+  const int32_t* live;     // live tiles in increasing order by runs (null: all tiles)
+  const int32_t* nlive;    // length of the live list (device)
   int32_t ntiles;
   int32_t nprob;
 };
@@ -80,11 +85,20 @@ hipError_t launch_batch_sweep(const SweepArgs& a, const BatchArgs& b, int mode, 
 hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double gamma,
                       const double* ih, const double* adv, double cfl, double* partial,
                       int nblocks, double* dt_out, hipStream_t stream);
+// The per-problem dt kernels.  A problem whose maximum wave rate is not a
+// positive finite number gets dt = 0, keeps its time and sets bit 0 of
+// *status (when given).  nlive, when given, is cleared for a rebuild of the
+// live list (launch_batch_live) after the kernel.
 hipError_t launch_batch_cfl(const double* U, int64_t total, const BatchArgs& b, double gamma,
                             double* t, double t_end, double cfl, unsigned long long* wmax,
-                            hipStream_t stream);
+                            int32_t* status, int32_t* nlive, hipStream_t stream);
 hipError_t launch_batch_dt(const BatchArgs& b, double* t, double t_end, double cfl,
-                           unsigned long long* wmax, hipStream_t stream);
+                           unsigned long long* wmax, int32_t* status, int32_t* nlive,
+                           hipStream_t stream);
+// The live-tile list: every tile with a problem of dt > 0, appended to
+// live[] in runs of consecutive tiles (nlive must be 0 before).
+hipError_t launch_batch_live(const BatchArgs& b, int32_t* live, int32_t* nlive,
+                             hipStream_t stream);
 hipError_t launch_axpy_state(double* y, const double* x, double a, int64_t n,
                              hipStream_t stream);
 hipError_t launch_lincomb(double* out, const double* x, double ax, const double* y, double ay,

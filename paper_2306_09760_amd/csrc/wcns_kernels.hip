@@ -75,10 +75,18 @@ __global__ void __launch_bounds__(256) cfl_final_kernel(const double* __restrict
 
 // The batch maxima use wave_max_bits (wcns_device.hpp).
 // dt_p = min(cfl / m, t_end - t_p) for a problem with t_p < t_end (0
-// otherwise); t_p advances by dt_p.
+// otherwise); t_p advances by dt_p.  A maximum rate m that is not positive and
+// finite (a non-finite or non-physical state; NaN bit patterns order above
+// every rate) stops the problem where it is: dt_p = 0, t_p unchanged, bit 0
+// of *status set.
 __device__ __forceinline__ void batch_dt(const BatchArgs& b, int p, double m, double* t,
-                                         double t_end, double cfl) {
+                                         double t_end, double cfl, int32_t* status) {
   const double tp = t[p];
+  if (!(m > 0.0 && m <= 1.79769313486231570815e308)) {
+    b.dtp[p] = 0.0;
+    if (status) atomicOr(status, 1);
+    return;
+  }
   double dt = cfl / m;
   double tn = tp + dt;
   if (!(dt < t_end - tp)) {
@@ -95,9 +103,11 @@ __global__ void __launch_bounds__(256) batch_cfl_kernel(const double* __restrict
                                                         int64_t total, BatchArgs b,
                                                         double gamma, double* __restrict__ t,
                                                         double t_end, double cfl,
-                                                        unsigned long long* wmax) {
+                                                        unsigned long long* wmax,
+                                                        int32_t* status, int32_t* nlive) {
   __shared__ unsigned long long red[4];
   const int p = blockIdx.x;
+  if (nlive && p == 0 && threadIdx.x == 0) *nlive = 0;
   if (wmax && threadIdx.x == 0) wmax[p] = 0;
   if (!(t[p] < t_end)) {  // uniform: the whole block leaves
     if (threadIdx.x == 0) b.dtp[p] = 0.0;
@@ -116,7 +126,7 @@ __global__ void __launch_bounds__(256) batch_cfl_kernel(const double* __restrict
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < 4; ++w) m = red[w] > m ? red[w] : m;  // m = red[0] here
-    batch_dt(b, p, __builtin_bit_cast(double, m), t, t_end, cfl);
+    batch_dt(b, p, __builtin_bit_cast(double, m), t, t_end, cfl, status);
   }
 }
 
@@ -125,8 +135,10 @@ __global__ void __launch_bounds__(256) batch_cfl_kernel(const double* __restrict
 // step's.  One thread per problem.
 __global__ void __launch_bounds__(256) batch_dt_kernel(BatchArgs b, double* __restrict__ t,
                                                        double t_end, double cfl,
-                                                       unsigned long long* __restrict__ wmax) {
+                                                       unsigned long long* __restrict__ wmax,
+                                                       int32_t* status, int32_t* nlive) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (nlive && p == 0) *nlive = 0;
   if (p >= b.nprob) return;
   const double m = __builtin_bit_cast(double, wmax[p]);
   wmax[p] = 0;
@@ -134,7 +146,27 @@ __global__ void __launch_bounds__(256) batch_dt_kernel(BatchArgs b, double* __re
     b.dtp[p] = 0.0;
     return;
   }
-  batch_dt(b, p, m, t, t_end, cfl);
+  batch_dt(b, p, m, t, t_end, cfl, status);
+}
+
+// The live-tile list: lane k tests tile k (live if one of its problems has
+// dt > 0); each wavefront appends its live tiles in order with one atomic,
+// so the list holds runs of up to 64 consecutive tiles.
+__global__ void __launch_bounds__(256) batch_live_kernel(BatchArgs b, int32_t* __restrict__ live,
+                                                         int32_t* __restrict__ nlive) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  bool on = false;
+  if (k < b.ntiles) {
+    const int p1 = b.tile_p1[k];
+    for (int p = b.tile_p0[k]; p <= p1 && !on; ++p) on = b.dtp[p] != 0.0;
+  }
+  const unsigned long long mask = __ballot(on);
+  if (mask == 0) return;  // uniform across the wavefront
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 0) base = atomicAdd(nlive, __popcll(mask));
+  base = __shfl(base, 0, 64);
+  if (on) live[base + __popcll(mask & ((1ull << lane) - 1ull))] = k;
 }
 
 // ------------------------------------------------------------ elementwise --
@@ -196,16 +228,24 @@ hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double ga
 
 hipError_t launch_batch_cfl(const double* U, int64_t total, const BatchArgs& b, double gamma,
                             double* t, double t_end, double cfl, unsigned long long* wmax,
-                            hipStream_t stream) {
+                            int32_t* status, int32_t* nlive, hipStream_t stream) {
   hipLaunchKernelGGL(batch_cfl_kernel, dim3(b.nprob), dim3(256), 0, stream, U, total, b, gamma,
-                     t, t_end, cfl, wmax);
+                     t, t_end, cfl, wmax, status, nlive);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_dt(const BatchArgs& b, double* t, double t_end, double cfl,
-                           unsigned long long* wmax, hipStream_t stream) {
+                           unsigned long long* wmax, int32_t* status, int32_t* nlive,
+                           hipStream_t stream) {
   hipLaunchKernelGGL(batch_dt_kernel, dim3((unsigned)ceil_div(b.nprob, 256)), dim3(256), 0,
-                     stream, b, t, t_end, cfl, wmax);
+                     stream, b, t, t_end, cfl, wmax, status, nlive);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_live(const BatchArgs& b, int32_t* live, int32_t* nlive,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(batch_live_kernel, dim3((unsigned)ceil_div(b.ntiles, 256)), dim3(256), 0,
+                     stream, b, live, nlive);
   return hipGetLastError();
 }
 

@@ -51,21 +51,16 @@ struct SweepLayout {
   static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
 
-// The FE specialisation runs at six waves per SIMD: the compiler keeps it
-// within 80 VGPRs without spilling, and the largest tile (NV = 3, 256
-// midpoints, 27.3 KB of LDS) still fits six workgroups in a CU's 160 KB.
-// The generic interpolation needs ~110 VGPRs and is left unconstrained
-// (capped at 80 it spills); the saturating FE one (SPEC_FE_SAT) needs ~118
-// and runs at four.
+// One tile (logical index `tile`) of a sweep; every lane of the workgroup
+// calls it.
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_GENERIC ? 1 : (SPEC == SPEC_FE ? 6 : 4))))
-    sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g, int mode) {
+__device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& b,
+                                           const TileGeom& g, int mode, int64_t tile,
+                                           double* smem) {
   using L = SweepLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TN = L::TN, TMW = L::TMW, SV = L::SV;
   constexpr int LW = L::LW, LTMW = L::LTMW;
   constexpr int NT = 256;
-  extern __shared__ double smem[];
   double* sU = smem;
   double* sR = sU + NV * SV;
   double* sW = sR + NR * TMW;
@@ -74,8 +69,6 @@ __global__ void __launch_bounds__(256)
   const int G = a.diff ? 5 : 4;
   const int TL = TM - (a.diff ? 5 : 3);
 
-  if ((int64_t)blockIdx.x >= g.ntiles) return;
-  const int64_t tile = xcd_tile(blockIdx.x, g.ntiles);
   int64_t base = 0, N = 0, stride = 1, i0;
   int ncol = 1;
   double ih = a.ih, dt = 0.0;
@@ -397,6 +390,36 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The FE specialisation runs at six waves per SIMD: the compiler keeps it
+// within 80 VGPRs without spilling, and the largest tile (NV = 3, 256
+// midpoints, 27.3 KB of LDS) still fits six workgroups in a CU's 160 KB.
+// The generic interpolation needs ~110 VGPRs and is left unconstrained
+// (capped at 80 it spills); the saturating FE one (SPEC_FE_SAT) needs ~118
+// and runs at four.
+// The sweep kernel: one tile per workgroup, in XCD-aware order.  A batch
+// launch with a live list (BatchArgs::live) maps workgroup b to list
+// position xcd_tile(b, nlive) (each XCD a contiguous range of the list, so
+// neighbouring tiles, which share halo lines, run on one L2 at about the same
+// time) and workgroups b >= nlive leave after reading the count: the list is
+// read on the device, so the host launches the same grid whatever the number
+// of live tiles.
+template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_GENERIC ? 1 : (SPEC == SPEC_FE ? 6 : 4))))
+    sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g, int mode) {
+  extern __shared__ double smem[];
+  int64_t tile;
+  if (BATCH && b.live) {
+    const int n = *b.nlive;
+    if ((int)blockIdx.x >= n) return;
+    tile = b.live[xcd_tile(blockIdx.x, n)];
+  } else {
+    if ((int64_t)blockIdx.x >= g.ntiles) return;
+    tile = xcd_tile(blockIdx.x, g.ntiles);
+  }
+  sweep_tile<NV, DIR, BATCH, SPEC, TM, W>(a, b, g, mode, tile, smem);
+}
+
 // --------------------------------------------------------------- launchers --
 static inline int64_t ceil_div64(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
@@ -412,21 +435,23 @@ bool sweep_shape_ok(int nv, int dir, int tm, int w) {
   return lds <= 64 * 1024;
 }
 
+template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
+static hipError_t sweep_launch(const SweepArgs& a, const BatchArgs& b, const TileGeom& g,
+                               int mode, size_t lds, hipStream_t s) {
+  hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC, TM, W>), dim3((unsigned)g.ntiles),
+                     dim3(256), lds, s, a, b, g, mode);
+  return hipGetLastError();
+}
+
 template <int NV, int DIR, bool BATCH, int TM, int W>
 static hipError_t sweep_go(const SweepArgs& a, const BatchArgs& b, const TileGeom& g, int mode,
                            hipStream_t s) {
   const size_t lds = sizeof(double) * SweepLayout<NV, TM, W>::lds_doubles;
   const int spec = spec_of(a.ip);
-  if (spec == SPEC_FE)
-    hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_FE, TM, W>), dim3((unsigned)g.ntiles),
-                       dim3(256), lds, s, a, b, g, mode);
-  else if (spec == SPEC_FE_SAT)
-    hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_FE_SAT, TM, W>),
-                       dim3((unsigned)g.ntiles), dim3(256), lds, s, a, b, g, mode);
-  else
-    hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC_GENERIC, TM, W>),
-                       dim3((unsigned)g.ntiles), dim3(256), lds, s, a, b, g, mode);
-  return hipGetLastError();
+  if (spec == SPEC_FE) return sweep_launch<NV, DIR, BATCH, SPEC_FE, TM, W>(a, b, g, mode, lds, s);
+  if (spec == SPEC_FE_SAT)
+    return sweep_launch<NV, DIR, BATCH, SPEC_FE_SAT, TM, W>(a, b, g, mode, lds, s);
+  return sweep_launch<NV, DIR, BATCH, SPEC_GENERIC, TM, W>(a, b, g, mode, lds, s);
 }
 
 template <int NV, int DIR, bool BATCH>

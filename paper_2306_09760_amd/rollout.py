@@ -40,6 +40,8 @@ from functools import lru_cache
 import numpy as np
 import torch
 
+from .solver import Plan
+
 
 @lru_cache(maxsize=64)
 def _tables(m_max: int, s_max: int):
@@ -178,6 +180,9 @@ def rollout(plan, U0: torch.Tensor, dt: torch.Tensor, nsteps: int, snapshots: in
     (3 nsteps states; ``snapshots`` is then ignored)."""
     if nsteps < 0:
         raise ValueError("nsteps must be >= 0")
+    if isinstance(plan, Plan):  # the library's plans check what reaches the kernels
+        plan._check_state(U0)
+        plan._dt(dt, optional=False)
     if stages:
         return _StagedRollout.apply(U0, plan, dt, int(nsteps))
     return _Rollout.apply(U0, plan, dt, int(nsteps), int(snapshots))

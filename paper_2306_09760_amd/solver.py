@@ -23,6 +23,26 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _aux(t, name, dtype, device, numel=None, min_numel=1, optional=True):
+    """Checks an auxiliary tensor before its address goes to the library: a
+    contiguous tensor of `dtype` on `device` with exactly `numel` (or at
+    least `min_numel`) elements; None passes when `optional`."""
+    if t is None:
+        if optional:
+            return None
+        raise _lib.WCNSError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise _lib.WCNSError(f"{name} must be a torch tensor")
+    if t.device != device or t.dtype != dtype or not t.is_contiguous():
+        raise _lib.WCNSError(f"{name} must be a contiguous {dtype} tensor on {device} "
+                             f"(got {t.dtype} on {t.device})")
+    if numel is not None and t.numel() != numel:
+        raise _lib.WCNSError(f"{name} must have {numel} elements (got {t.numel()})")
+    if t.numel() < min_numel:
+        raise _lib.WCNSError(f"{name} must have at least {min_numel} elements")
+    return t
+
+
 def _require_device(device):
     if not torch.cuda.is_available():
         raise _lib.WCNSError("no HIP device is visible: the WCNS library runs on the GPU only")
@@ -67,16 +87,23 @@ class Plan:
         if tuple(U.shape) != self.shape:
             raise _lib.WCNSError(f"state shape {tuple(U.shape)} != {self.shape}")
 
+    def _dt(self, dt, optional=True):
+        return _aux(dt, "dt", torch.float64, self.device, optional=optional)
+
+    def _status(self, status):
+        return _aux(status, "status", torch.int32, self.device)
+
     def residual(self, U, out=None):
         self._check_state(U)
         R = torch.empty_like(U) if out is None else out
+        self._check_state(R)
         check(lib().wcns_residual(self._h, _ptr(U), _ptr(R), _ptr(self.work), _stream()),
               "wcns_residual")
         return R
 
     def cfl_dt(self, U, cfl=0.5, out=None):
         self._check_state(U)
-        dt = self.dt if out is None else out
+        dt = self.dt if out is None else self._dt(out, optional=False)
         check(lib().wcns_cfl_dt(self._h, _ptr(U), cfl, _ptr(dt), _ptr(self.work), _stream()),
               "wcns_cfl_dt")
         return dt
@@ -84,6 +111,8 @@ class Plan:
     def rk3_step(self, U, dt=None, cfl=0.5, status=None):
         """In-place SSP-RK3 step; dt: device tensor (1,) or None (cfl-limited)."""
         self._check_state(U)
+        self._dt(dt)
+        self._status(status)
         check(lib().wcns_rk3_step(self._h, _ptr(U), _ptr(self.work), _ptr(dt), cfl,
                                   _ptr(status), _stream()), "wcns_rk3_step")
         return U
@@ -92,6 +121,8 @@ class Plan:
         """rk3_step that also writes the stage states U^(1), U^(2) to U1, U2."""
         for X in (U, U1, U2):
             self._check_state(X)
+        self._dt(dt)
+        self._status(status)
         check(lib().wcns_rk3_step_stages(self._h, _ptr(U), _ptr(U1), _ptr(U2), _ptr(self.work),
                                          _ptr(dt), cfl, _ptr(status), _stream()),
               "wcns_rk3_step_stages")
@@ -100,6 +131,8 @@ class Plan:
     def rk4_step(self, U, dt=None, cfl=0.3, status=None):
         """In-place step of the four-stage scheme of eq. 16; dt as rk3_step."""
         self._check_state(U)
+        self._dt(dt)
+        self._status(status)
         check(lib().wcns_rk4_step(self._h, _ptr(U), _ptr(self.work), _ptr(dt), cfl,
                                   _ptr(status), _stream()), "wcns_rk4_step")
         return U
@@ -135,8 +168,10 @@ class Plan:
         self._check_state(U)
         if hist is None:
             hist = torch.zeros((3, 3, nbins), dtype=torch.int64, device=self.device)
-        if hist.dtype != torch.int64 or not hist.is_contiguous() or hist.numel() % 9:
-            raise _lib.WCNSError("hist must be a contiguous int64 tensor of 3 x 3 x nbins")
+        if hist.dtype != torch.int64 or not hist.is_contiguous() or hist.numel() % 9 or \
+                hist.device != self.device:
+            raise _lib.WCNSError("hist must be a contiguous int64 tensor of 3 x 3 x nbins "
+                                 "on the plan's device")
         check(lib().wcns_weight_histogram(self._h, _ptr(U), _ptr(hist), hist.numel() // 9,
                                           _stream()), "wcns_weight_histogram")
         return hist
@@ -147,6 +182,7 @@ class Plan:
         self._check_state(Rbar)
         if Ubar is None:
             Ubar = torch.zeros_like(U)
+        self._check_state(Ubar)
         check(lib().wcns_residual_adjoint(self._h, _ptr(U), _ptr(Rbar), _ptr(Ubar),
                                           _ptr(self.work), _stream()), "wcns_residual_adjoint")
         return Ubar
@@ -157,6 +193,7 @@ class Plan:
         recomputation."""
         self._check_state(Un)
         self._check_state(lam)
+        self._dt(dt, optional=False)
         if stages is None:
             check(lib().wcns_rk3_step_adjoint(self._h, _ptr(Un), _ptr(lam), _ptr(self.work),
                                               _ptr(dt), _stream()), "wcns_rk3_step_adjoint")
@@ -227,15 +264,24 @@ class BatchPlan:
         if tuple(U.shape) != self.shape:
             raise _lib.WCNSError(f"state shape {tuple(U.shape)} != {self.shape}")
 
+    def _t(self, t):
+        return _aux(t, "t", torch.float64, self.device, numel=self.nprob, optional=False)
+
+    def _status(self, status):
+        return _aux(status, "status", torch.int32, self.device)
+
     def residual(self, U, out=None):
         self._check_state(U)
         R = torch.empty_like(U) if out is None else out
+        self._check_state(R)
         check(lib().wcns_batch_residual(self._h, _ptr(U), _ptr(R), _ptr(self.work), _stream()),
               "wcns_batch_residual")
         return R
 
     def rk3_step(self, U, t, t_end, cfl=0.5, status=None):
         self._check_state(U)
+        self._t(t)
+        self._status(status)
         check(lib().wcns_batch_rk3_step(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
                                         float(cfl), _ptr(status), _stream()), "wcns_batch_rk3_step")
         return U
@@ -244,6 +290,8 @@ class BatchPlan:
         """nsteps rk3_step calls in one: each step's CFL maximum is taken by
         the previous step's last stage (see include/wcns.h)."""
         self._check_state(U)
+        self._t(t)
+        self._status(status)
         check(lib().wcns_batch_rk3_steps(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
                                          float(cfl), int(nsteps), _ptr(status), _stream()),
               "wcns_batch_rk3_steps")
@@ -252,6 +300,7 @@ class BatchPlan:
     def cfl(self, U, t, t_end, cfl=0.5):
         """Per-problem dt into the workspace; t += dt (first kernel of a step)."""
         self._check_state(U)
+        self._t(t)
         check(lib().wcns_batch_cfl(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
                                    float(cfl), _stream()), "wcns_batch_cfl")
 
@@ -259,6 +308,7 @@ class BatchPlan:
         """One SSP-RK3 stage with the dt of the last cfl()/rk3_step()."""
         for x in (Uk, U0, out):
             self._check_state(x)
+        self._status(status)
         check(lib().wcns_batch_stage(self._h, int(stage), _ptr(Uk), _ptr(U0), _ptr(out),
                                      _ptr(self.work), _ptr(status), _stream()), "wcns_batch_stage")
         return out
@@ -284,8 +334,13 @@ class BatchPlan:
                     fused=True):
         """Steps every problem to t_end (host checks completion every
         ``check_every`` steps): with ``fused`` in rk3_steps calls, else one
-        rk3_step call per step (graph-replayed if set_graph).  Returns (t,
+        rk3_step call per step (graph-replayed if set_graph).  Raises
+        WCNSError when a problem's state goes non-physical (the library then
+        stops that problem and sets bit 0 of the status word).  Returns (t,
         steps issued)."""
+        if status is None:
+            status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._status(status)
         t = torch.zeros(self.nprob, dtype=torch.float64, device=self.device)
         steps = 0
         while steps < max_steps:
@@ -295,6 +350,10 @@ class BatchPlan:
                 for _ in range(check_every):
                     self.rk3_step(U, t, t_end, cfl, status)
             steps += check_every
+            if int(status.item()) & 1:
+                bad = torch.nonzero(t < t_end).flatten().tolist()
+                raise _lib.WCNSError(f"non-physical state after {steps} steps (problems not at "
+                                     f"t_end: {bad[:16]}{' ...' if len(bad) > 16 else ''})")
             if bool((t >= t_end).all().item()):
                 break
         return t, steps

@@ -148,3 +148,36 @@ def test_product_path_has_no_cpu_fallback():
         from paper_2306_09760_amd import Plan, WCNSError
         with pytest.raises(WCNSError):
             Plan(system="euler", ndim=1, n=(32,))
+
+
+def test_adjoint_step_rejects_aliasing_on_host(L):
+    """The reverse step writes lambda in place while tiles still read the
+    states, and keeps two stage cotangents in the workspace: overlapping
+    arguments are rejected before anything is enqueued (the pointers here
+    are never dereferenced)."""
+    lib = L.lib()
+    d = L.make_desc(system="euler", ndim=1, n=(32,))
+    h = C.c_void_p()
+    assert lib.wcns_plan_create(C.byref(d), C.byref(h)) == 0
+    try:
+        sb = 8 * lib.wcns_state_elems(h)
+        wb = lib.wcns_workspace_bytes(h)
+        base = 1 << 40  # distinct, non-overlapping fake addresses
+        Un, U1, U2, lam, dt = (C.c_void_p(base + k * (1 << 30)) for k in range(5))
+        work = C.c_void_p(base + 8 * (1 << 30))
+        step = lib.wcns_rk3_step_adjoint
+        stages = lib.wcns_rk3_step_adjoint_stages
+        assert step(h, Un, Un, work, dt, None) == L.WCNS_EINVAL            # lambda == Un
+        assert "lambda" in lib.wcns_last_error().decode()
+        assert step(h, Un, C.c_void_p(base + 8), work, dt, None) == L.WCNS_EINVAL  # overlap
+        assert step(h, Un, work, work, dt, None) == L.WCNS_EINVAL          # lambda in work
+        assert stages(h, Un, U1, U2, U1, work, dt, None) == L.WCNS_EINVAL  # lambda == U1
+        assert stages(h, Un, U1, U2, U2, work, dt, None) == L.WCNS_EINVAL  # lambda == U2
+        # a stage state inside the workspace's cotangent buffers (the last
+        # two states' worth of the first five)
+        inside = C.c_void_p(work.value + 3 * sb)
+        assert 3 * sb < wb
+        assert stages(h, Un, inside, U2, lam, work, dt, None) == L.WCNS_EINVAL
+        assert "cotangent" in lib.wcns_last_error().decode()
+    finally:
+        lib.wcns_plan_destroy(h)

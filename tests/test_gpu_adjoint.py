@@ -150,3 +150,35 @@ def test_adjoint_matches_central_differences_of_gpu_forward(lib, W):
         fd = float(np.sum(Rb * (Rp - Rm))) / (2 * eps)
         best = min(best, abs(fd - float(np.sum(Ub * V))) / abs(fd))
     assert best < 1e-6
+
+
+@pytest.mark.parametrize("xi", [200.0, 1000.0, 1e6])
+def test_adjoint_dot_product_fe_large_xi_1d(lib, ora, W, xi):
+    """FE weights at the steepnesses of the other device evaluations of the
+    map (one exponential per map with a reciprocal per term at 200, one per
+    term at 1000, the saturating terms at 1e6): the adjoint against the
+    oracle's dual JVP, on a smooth state with a sharp density block (every
+    field resolved: on a shock tube evolved from piecewise-constant data the
+    flat regions leave smoothness indicators at rounding-noise level next to
+    the waves, and the exact derivative there is set by that noise; the
+    oracle's own JVP then disagrees with its central differences)."""
+    prob, U = W.random_smooth_state(27, 1, (60,), amp=0.25)
+    U = U.copy()
+    U[0, 20:38] *= 1.6
+    prob["bc"] = "transmissive"
+    O = ora.Problem(**prob, weights="fe", xi=xi)
+    say("adjoint 1d fe xi =", xi)
+    G = lib.Plan(**prob, weights="fe", xi=xi)
+    _dot_check(G, O, U, np.random.default_rng(7))
+
+
+@pytest.mark.parametrize("xi", [200.0, 1000.0, 1e6])
+def test_adjoint_dot_product_fe_large_xi_2d(lib, ora, W, xi):
+    prob, U = W.random_smooth_state(26, 2, (20, 17), amp=0.25)
+    U = U.copy()
+    U[0, 5:11, 4:9] *= 1.6  # a density block with sharp edges
+    prob["bc"] = ("transmissive", "periodic")
+    say("adjoint 2d fe xi =", xi)
+    G = lib.Plan(**prob, weights="fe", xi=xi)
+    O = ora.Problem(**prob, weights="fe", xi=xi)
+    _dot_check(G, O, U, np.random.default_rng(8))

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import rel_err, run_tolerance, say, to_dev, to_host
+from gpu_util import end_bar, rel_err, say, shadowed_run_to_time, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -74,15 +74,14 @@ def test_weno_steps_and_run(lib, ora, W):
         assert bad == 0
         _check(to_host(Ud), U1, f"weno {method} step")
     say("weno sod run")
-    Ud = to_dev(U)
-    G.run_to_time(Ud, 0.15, cfl=0.5)
+    Of = ora.Problem(**prob, family="weno", weights="fe", xi=100.0, variant="fma")
+    Ud, steps, t, worst, ratio = shadowed_run_to_time(G, O, U, 0.15, cfl=0.5, Of=Of)
     Uo, _, _, bad = O.run_to_time(U, 0.15, cfl=0.5)
-    Uf, _, _, _ = ora.Problem(**prob, family="weno", weights="fe", xi=100.0,
-                              variant="fma").run_to_time(U, 0.15, cfl=0.5)
-    tol, ptol, spread = run_tolerance(Uo, Uf)
+    Uf, _, _, _ = Of.run_to_time(U, 0.15, cfl=0.5)
+    tol, ptol, spread, informative = end_bar(Uo, Uf, ratio.value)
     n, p = rel_err(to_host(Ud), Uo)
-    say("  spread", spread, "gpu vs oracle", n, p)
-    assert bad == 0 and n <= tol and p <= ptol
+    say("  steps", steps, "worst step", worst, "spread", spread, "gpu vs oracle", n, p)
+    assert bad == 0 and informative and n <= tol and p <= ptol
 
 
 def test_weno_unsupported_calls_refuse(lib, W):
