@@ -132,6 +132,24 @@ wcns_status wcns_cfl_dt(wcns_plan* plan, const double* U, double cfl, double* dt
 wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev,
                           double cfl, int32_t* status_dev, void* stream);
 
+/* wcns_rk3_step for callers that cannot allocate (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the same
+   step, the same kernels and bitwise the same result, with no workspace
+   argument.  The stage states, the residual accumulator (2D/3D), the CFL
+   block maxima and dt live in a device array inside the library, 48 MiB
+   per GPU, held until the process ends: the plan must need at most that
+   (2 states, 3 in 2D/3D, plus 16.25 KB: a state of up to about 3.1 M
+   doubles in 1D and 2.1 M in 2D/3D), else WCNS_EINVAL before anything is
+   enqueued.
+   The call allocates nothing (no hipMalloc, no hipFree; the first call on a
+   device looks up the array's address there).  Every call on one GPU uses
+   the same array: calls that overlap on the device (two streams, two host
+   threads) race and must not be issued; nothing in the array needs to be
+   zero beforehand (every buffer is written before it is read).  dt_dev,
+   cfl, status_dev and stream as for wcns_rk3_step.  Graph-capturable. */
+wcns_status wcns_rk3_step_noalloc(wcns_plan* plan, double* U, const double* dt_dev, double cfl,
+                                  int32_t* status_dev, void* stream);
+
 /* wcns_rk3_step that also leaves its stage states: U1 <- U^(1) = U^n + dt
    L(U^n), U2 <- U^(2) = 3/4 U^n + 1/4 (U^(1) + dt L(U^(1))), then U <-
    U^{n+1}.  U1, U2: device arrays of wcns_state_elems doubles owned by the

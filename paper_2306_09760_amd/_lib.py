@@ -26,6 +26,7 @@ SCHEMES = {"wcns": 0, "weno": 1}
 EXPORTS = [
     "wcns_desc_init", "wcns_plan_create", "wcns_plan_destroy", "wcns_state_elems",
     "wcns_workspace_bytes", "wcns_residual", "wcns_cfl_dt", "wcns_rk3_step",
+    "wcns_rk3_step_noalloc",
     "wcns_rk3_step_stages", "wcns_rk4_step",
     "wcns_weight_histogram",
     "wcns_residual_adjoint", "wcns_rk3_step_adjoint", "wcns_rk3_step_adjoint_stages",
@@ -78,6 +79,7 @@ def lib():
         "wcns_residual": (st, [vp, vp, vp, vp, vp]),
         "wcns_cfl_dt": (st, [vp, vp, C.c_double, vp, vp, vp]),
         "wcns_rk3_step": (st, [vp, vp, vp, vp, C.c_double, vp, vp]),
+        "wcns_rk3_step_noalloc": (st, [vp, vp, vp, C.c_double, vp, vp]),
         "wcns_rk3_step_stages": (st, [vp, vp, vp, vp, vp, vp, C.c_double, vp, vp]),
         "wcns_rk4_step": (st, [vp, vp, vp, vp, C.c_double, vp, vp]),
         "wcns_weight_histogram": (st, [vp, vp, vp, C.c_int32, vp]),

@@ -469,6 +469,38 @@ wcns_status rk3_step_into(wcns_plan* plan, double* U, double* W1, double* W2, vo
                        status_dev, stream);
 }
 
+// The device array behind wcns_rk3_step_noalloc (each GPU holds its own copy
+// until the process ends).  In host code `scratch` names a host-side stand-in;
+// its device address on each GPU is taken once, with that GPU current.
+constexpr size_t kScratchBytes = size_t(48) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+wcns_status scratch_address(void** out) {
+  int dev = 0;
+  WCNS_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(WCNS_EUNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    WCNS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(WCNS_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return WCNS_OK;
+}
+
+// Bytes of scratch a step of this plan needs: the two stage states, the
+// residual accumulator (2D/3D only), the CFL block maxima and dt.
+size_t noalloc_bytes(const wcns_plan* P) {
+  const size_t state = align256(sizeof(double) * P->nv * P->npts);
+  return 2 * state + (P->d.ndim > 1 ? state : 0) + align256(sizeof(double) * P->ncfl) + 256;
+}
 }  // namespace
 
 wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* dt_dev, double cfl,
@@ -478,6 +510,36 @@ wcns_status wcns_rk3_step(wcns_plan* plan, double* U, void* work, const double* 
   char* w = (char*)work;
   return rk3_step_into(plan, U, (double*)(w + plan->off_W1), (double*)(w + plan->off_W2), work,
                        dt_dev, cfl, status_dev, stream);
+}
+
+wcns_status wcns_rk3_step_noalloc(wcns_plan* plan, double* U, const double* dt_dev, double cfl,
+                                  int32_t* status_dev, void* stream) {
+  g_err.clear();
+  if (!plan || !U) return fail(WCNS_EINVAL, "NULL argument");
+  const size_t need = noalloc_bytes(plan);
+  if (need > kScratchBytes)
+    return fail(WCNS_EINVAL,
+                "wcns_rk3_step_noalloc needs %zu bytes of scratch for this plan, above its "
+                "maximum of %zu (states of at most about %zu doubles); use wcns_rk3_step",
+                need, kScratchBytes, (kScratchBytes - 65536) / (plan->d.ndim > 1 ? 3 : 2) / 8);
+  if (!dt_dev && !(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0 when dt_dev is NULL");
+  void* base = nullptr;
+  const wcns_status st = scratch_address(&base);
+  if (st != WCNS_OK) return st;
+  char* w = (char*)base;
+  const size_t state = align256(sizeof(double) * plan->nv * plan->npts);
+  double* W1 = (double*)w;
+  double* W2 = (double*)(w + state);
+  size_t o = 2 * state;
+  double* Racc = nullptr;
+  if (plan->d.ndim > 1) {
+    Racc = (double*)(w + o);
+    o += state;
+  }
+  double* partial = (double*)(w + o);
+  o += align256(sizeof(double) * plan->ncfl);
+  double* dtw = (double*)(w + o);
+  return rk3_step_bufs(plan, U, W1, W2, Racc, partial, dtw, dt_dev, cfl, status_dev, stream);
 }
 
 wcns_status wcns_rk3_step_stages(wcns_plan* plan, double* U, double* U1, double* U2, void* work,

@@ -117,6 +117,17 @@ class Plan:
                                   _ptr(status), _stream()), "wcns_rk3_step")
         return U
 
+    def rk3_step_noalloc(self, U, dt=None, cfl=0.5, status=None):
+        """rk3_step with the step's buffers in the library's own device array
+        (wcns_rk3_step_noalloc: no workspace, no allocation; calls on one GPU
+        must not overlap)."""
+        self._check_state(U)
+        self._dt(dt)
+        self._status(status)
+        check(lib().wcns_rk3_step_noalloc(self._h, _ptr(U), _ptr(dt), cfl, _ptr(status),
+                                          _stream()), "wcns_rk3_step_noalloc")
+        return U
+
     def rk3_step_stages(self, U, U1, U2, dt=None, cfl=0.5, status=None):
         """rk3_step that also writes the stage states U^(1), U^(2) to U1, U2."""
         for X in (U, U1, U2):

@@ -181,3 +181,19 @@ def test_adjoint_step_rejects_aliasing_on_host(L):
         assert "cotangent" in lib.wcns_last_error().decode()
     finally:
         lib.wcns_plan_destroy(h)
+
+
+def test_noalloc_step_refuses_plans_beyond_its_array_on_host(L):
+    """wcns_rk3_step_noalloc checks the plan against its 48 MiB array before
+    any device work (the pointers here are never dereferenced)."""
+    lib = L.lib()
+    d = L.make_desc(system="euler", ndim=2, n=(1024, 1024))   # 3 x 32 MiB of states
+    h = C.c_void_p()
+    assert lib.wcns_plan_create(C.byref(d), C.byref(h)) == 0
+    try:
+        st = lib.wcns_rk3_step_noalloc(h, C.c_void_p(1 << 40), None, 0.5, None, None)
+        assert st == L.WCNS_EINVAL
+        assert "scratch" in lib.wcns_last_error().decode()
+        assert lib.wcns_rk3_step_noalloc(h, None, None, 0.5, None, None) == L.WCNS_EINVAL
+    finally:
+        lib.wcns_plan_destroy(h)
