@@ -254,6 +254,12 @@ wcns_status wcns_batch_residual(wcns_batch_plan* plan, const double* U, double* 
 wcns_status wcns_batch_rk3_step(wcns_batch_plan* plan, double* U, void* work, double* t_dev,
                                 double t_end, double cfl, int32_t* status_dev, void* stream);
 wcns_status wcns_batch_set_graph(wcns_batch_plan* plan, int32_t enable);
+/* Copies the step size dt_p each problem took in the last step (or that the
+   last wcns_batch_cfl set; 0 for a finished or stopped problem) from `work`
+   to dt_dev, a device array of nprob doubles: an asynchronous
+   device-to-device copy on `stream`. */
+wcns_status wcns_batch_last_dt(const wcns_batch_plan* plan, const void* work, double* dt_dev,
+                               void* stream);
 /* nsteps >= 0 calls of wcns_batch_rk3_step in one (never graph-captured):
    the same states and times bit for bit for physical states.  Each step's
    dt_p still comes from the CFL bound on that step's starting state (the

@@ -76,6 +76,7 @@ def lib(variant: str = "plain"):
         L.ora_rk3_step.argtypes = [D, P, C.c_double]
         L.ora_rk3_step_jvp.argtypes = [D, P, P, C.c_double]
         L.ora_run_steps.argtypes = [D, P, C.c_double, C.c_double, C.c_int64]
+        L.ora_run_dt_sequence.argtypes = [D, P, P, C.c_int64]
         L.ora_run_to_time.argtypes = [D, P, C.c_double, C.c_double, C.c_int64,
                                       C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.ora_rk4_step.argtypes = [D, P, C.c_double]
@@ -190,6 +191,13 @@ class Problem:
     def run_steps(self, U, nsteps, cfl=0.5, dt=0.0):
         U = self._u(U).copy()
         bad = lib(self.variant).ora_run_steps(self._ref(), _p(U), cfl, dt, int(nsteps))
+        return U, bad
+
+    def run_dt_sequence(self, U, dts):
+        """SSP-RK3 steps of the given sizes (zeros skipped)."""
+        U = self._u(U).copy()
+        dts = np.ascontiguousarray(dts, dtype=np.float64)
+        bad = lib(self.variant).ora_run_dt_sequence(self._ref(), _p(U), _p(dts), len(dts))
         return U, bad
 
     def rk4_step(self, U, dt):

@@ -896,6 +896,15 @@ int ora_run_steps(const Desc* D, double* U, double cfl, double dt_fixed, int64_t
   return bad;
 }
 
+// SSP-RK3 steps of the given sizes dts[0 .. n-1] (steps of size 0 are
+// skipped): the same run as another integrator that took those steps.
+int ora_run_dt_sequence(const Desc* D, double* U, const double* dts, int64_t n) {
+  int bad = 0;
+  for (int64_t k = 0; k < n; ++k)
+    if (dts[k] > 0.0) bad |= ora::rk3_step(*D, U, dts[k]);
+  return bad;
+}
+
 // March to t_end with the CFL step, the last step clipped to land on t_end.
 int ora_run_to_time(const Desc* D, double* U, double cfl, double t_end, int64_t max_steps,
                     int64_t* steps_done, double* t_done) {

@@ -1124,6 +1124,16 @@ wcns_status wcns_batch_stage(wcns_batch_plan* B, int32_t stage, const double* Uk
   return WCNS_OK;
 }
 
+wcns_status wcns_batch_last_dt(const wcns_batch_plan* B, const void* work, double* dt_dev,
+                               void* stream) {
+  g_err.clear();
+  if (!B || !work || !dt_dev) return fail(WCNS_EINVAL, "NULL argument");
+  WCNS_HIP(hipMemcpyAsync(dt_dev, (const char*)work + B->off_dtp, sizeof(double) * B->nprob,
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream),
+           "copy of the per-problem dt");
+  return WCNS_OK;
+}
+
 wcns_status wcns_batch_set_graph(wcns_batch_plan* B, int32_t enable) {
   g_err.clear();
   if (!B) return fail(WCNS_EINVAL, "NULL plan");

@@ -324,6 +324,15 @@ class BatchPlan:
                                      _ptr(self.work), _ptr(status), _stream()), "wcns_batch_stage")
         return out
 
+    def last_dt(self, out=None):
+        """The dt each problem took in the last step (0: finished or stopped),
+        copied on the device into `out` (float64, nprob) or a new tensor."""
+        out = torch.empty(self.nprob, dtype=torch.float64, device=self.device) if out is None \
+            else _aux(out, "out", torch.float64, self.device, numel=self.nprob, optional=False)
+        check(lib().wcns_batch_last_dt(self._h, _ptr(self.work), _ptr(out), _stream()),
+              "wcns_batch_last_dt")
+        return out
+
     def set_graph(self, enable=True):
         check(lib().wcns_batch_set_graph(self._h, 1 if enable else 0), "wcns_batch_set_graph")
 

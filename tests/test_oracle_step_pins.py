@@ -249,3 +249,17 @@ def test_op_count_of_a_residual_is_the_sum_of_its_parts(ora, W, bc, diff):
     diffop = _ops(add=6, mul=3, div=1)
     expect = _plus(mid, FLUX1, diffop, times=[N + 2 * G - 5, N + 2, 3 * N])
     assert P.count_residual_ops(U) == expect
+
+
+def test_run_dt_sequence_is_the_steps_it_lists(ora, W):
+    """The oracle driven by a given step sequence (zeros skipped) is the
+    same as its single steps of those sizes."""
+    prob, U, _ = W.shock_tube(1.0, 0.75, 1.0, 0.125, 0.0, 0.1, 100)
+    O = ora.Problem(**prob, weights="fe", xi=100.0)
+    dts = [1e-3, 0.0, 7e-4, 1.2e-3]
+    ref = U.copy()
+    for dt in dts:
+        if dt > 0:
+            ref, _ = O.rk3_step(ref, dt)
+    got, bad = O.run_dt_sequence(U, dts)
+    assert bad == 0 and np.array_equal(got, ref)
