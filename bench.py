@@ -143,6 +143,12 @@ def sweep_kernels(seed):
     Rb, Ub = torch.ones_like(U), torch.zeros_like(U)
     out["2d_adjoint_1024"] = {"residual_adjoint_ms": round(timed(lambda: P.residual_adjoint(U, Rb, Ub), 3), 4),
                               "points": 1024 * 1024}
+    del P, U, Rb, Ub
+    # a plain 1 GiB device copy: the HBM counters' calibration
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 
