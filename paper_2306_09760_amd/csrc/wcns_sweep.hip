@@ -27,7 +27,9 @@
 // load | roe and flux | diff are synchronised.
 // LDS (doubles): sU[NV][TM+5][W] | sR[NR][TM*W] | sW[2 NV][TM*W] | the
 // 64-entry exp table; the flux overwrites sW rows 0..NV-1 (each task reads
-// its midpoint's two states before writing that midpoint's flux).
+// its midpoint's two states before writing that midpoint's flux).  On the
+// register path (sweep_reg: 4 and 5 variables, TM*W = 256) each lane keeps
+// its midpoint's Roe state in registers and sR is left out.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -37,16 +39,37 @@
 
 namespace wcns {
 
+#ifndef WCNS_REG_MIN_NV  // fewest variables of a register-path tile
+#define WCNS_REG_MIN_NV 4
+#endif
+
+// With TM W = 256 every lane owns one midpoint column through the Roe,
+// interpolation and flux phases.  From WCNS_REG_MIN_NV variables on, that
+// lane keeps its Roe state in registers instead of LDS: the 5-variable tile
+// then needs 31 KB of LDS instead of 43 KB (five workgroups per CU instead of
+// three), the 4-variable one 25 KB instead of 35 KB.
+constexpr bool sweep_reg(int nv, int tmw) { return tmw == 256 && nv > 1 && nv >= WCNS_REG_MIN_NV; }
+
+// LDS doubles of a tile: nodes sU[NV][TM+5][W] | Roe states sR[NR][TM W]
+// (none on the register path) | interpolated states sW[2 NV][TM W] | the
+// 64-entry exp table.
+constexpr size_t sweep_lds_doubles(int nv, int tm, int w) {
+  const size_t nr = (nv > 1 && !sweep_reg(nv, tm * w)) ? (size_t)nv + 1 : 0;
+  return (size_t)nv * (tm + 5) * w + (nr + 2 * (size_t)nv) * ((size_t)tm * w) + 64;
+}
+
 template <int NV, int TM, int W>
 struct SweepLayout {
   static constexpr int ND = NV > 1 ? NV - 2 : 1;
-  static constexpr int NR = NV > 1 ? NV - 2 + 3 : 0;  // vel[ND], H, c, ic
+  static constexpr bool REG = sweep_reg(NV, TM * W);
+  static constexpr int NR = (NV > 1 && !REG) ? NV - 2 + 3 : 0;  // vel[ND], H, c, ic
   static constexpr int TN = TM + 5;                    // nodes per column
   static constexpr int TMW = TM * W;                   // midpoints per tile
   static constexpr int SV = TN * W;                    // LDS stride between variables
   static constexpr int LW = W == 1 ? 0 : W == 2 ? 1 : W == 4 ? 2 : W == 8 ? 3 : 4;
   static constexpr int LTMW = TMW == 128 ? 7 : 8;
-  static constexpr size_t lds_doubles = (size_t)NV * SV + (size_t)(NR + 2 * NV) * TMW + 64;
+  static constexpr size_t lds_doubles = sweep_lds_doubles(NV, TM, W);
+  static_assert(lds_doubles == (size_t)NV * SV + (size_t)(NR + 2 * NV) * TMW + 64, "LDS layout");
   static_assert(TMW == 128 || TMW == 256, "tile must hold 128 or 256 midpoints");
   static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
@@ -60,6 +83,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
   using L = SweepLayout<NV, TM, W>;
   constexpr int ND = L::ND, NR = L::NR, TN = L::TN, TMW = L::TMW, SV = L::SV;
   constexpr int LW = L::LW, LTMW = L::LTMW;
+  constexpr bool REG = L::REG;
   constexpr int NT = 256;
   double* sU = smem;
   double* sR = sU + NV * SV;
@@ -188,7 +212,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
   // the Roe, interpolation and flux phases need no barrier between them.
   constexpr bool OWN = (TMW == NT);
   const bool proj = (NV > 1) && a.pp.charproj;
-  if constexpr (NV > 1) {
+  RoeState<ND> rsq{};  // the register path: Roe state of the lane's midpoint column
+  if constexpr (REG) {
+    if (proj) {
+      const double* u = sU + tid + 2 * W;
+      double UA[NV], UB[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UA[v] = u[v * SV];
+        UB[v] = u[v * SV + W];
+      }
+      rsq = roe_average<ND>(UA, UB, a.pp.gamma);
+    }
+  } else if constexpr (NV > 1) {
     if (proj) {
 #pragma unroll 1
       for (int q = tid; q < TMW; q += NT) {
@@ -225,15 +261,35 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
         const double* r = sR + rem;
         if (v >= 2 && v < NV - 1) {  // shear field: m_ax - vel_ax rho
           const int ax = tangential_axis<ND, DIR>(v - 2);
-          const double va = r[ax * TMW];
+          double va;
+          if constexpr (REG) {
+            va = rsq.vel[0];
+#pragma unroll
+            for (int k = 1; k < ND; ++k) va = (ax == k) ? rsq.vel[k] : va;
+          } else {
+            va = r[ax * TMW];
+          }
           const double* um = u + (1 + ax) * SV;
 #pragma unroll
           for (int j = 0; j < 6; ++j) w[j] = __builtin_fma(-va, u[j * W], um[j * W]);
         } else {
           RoeState<ND> rs;
+          if constexpr (REG) {
+            // recomputed per field from vel and ic, which are all the loop
+            // keeps of the Roe state besides H and c (the empty asm hides
+            // that they are loop-invariant)
 #pragma unroll
-          for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
-          rs.ic = r[(ND + 2) * TMW];
+            for (int k = 0; k < ND; ++k) {
+              rs.vel[k] = rsq.vel[k];
+              asm volatile("" : "+v"(rs.vel[k]));
+            }
+            rs.ic = rsq.ic;
+            asm volatile("" : "+v"(rs.ic));
+          } else {
+#pragma unroll
+            for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
+            rs.ic = r[(ND + 2) * TMW];
+          }
           roe_derived<ND>(rs, a.pp.gamma);
           double l[NV];
           field_row<ND, DIR>(rs, v, l);
@@ -282,14 +338,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
         WR[v] = sW[(NV + v) * TMW + q];
       }
       if (proj) {
-        RoeState<ND> rs;
-        const double* r = sR + q;
+        RoeState<ND> rs = rsq;
+        if constexpr (!REG) {
+          const double* r = sR + q;
 #pragma unroll
-        for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
-        rs.H = r[(ND + 0) * TMW];
-        rs.c = r[(ND + 1) * TMW];
-        rs.ic = r[(ND + 2) * TMW];
-        roe_derived<ND>(rs, a.pp.gamma);
+          for (int k = 0; k < ND; ++k) rs.vel[k] = r[k * TMW];
+          rs.H = r[(ND + 0) * TMW];
+          rs.c = r[(ND + 1) * TMW];
+          rs.ic = r[(ND + 2) * TMW];
+          roe_derived<ND>(rs, a.pp.gamma);
+        }
         unproject<ND, DIR>(rs, WL, UL);
         unproject<ND, DIR>(rs, WR, UR);
       } else {
@@ -393,6 +451,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
 // The FE specialisation runs at six waves per SIMD: the compiler keeps it
 // within 80 VGPRs without spilling, and the largest tile (NV = 3, 256
 // midpoints, 27.3 KB of LDS) still fits six workgroups in a CU's 160 KB.
+// The register path runs at five (at most 102 VGPRs; 86-90 used, no spills):
+// at six its Roe state spills, and LDS allows five 5-variable tiles per CU
+// (four for the 32 x 8 tile) against three before.
 // The generic interpolation needs ~110 VGPRs and is left unconstrained
 // (capped at 80 it spills); the saturating FE one (SPEC_FE_SAT) needs ~118
 // and runs at four.
@@ -403,9 +464,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
 // time) and workgroups b >= nlive leave after reading the count: the list is
 // read on the device, so the host launches the same grid whatever the number
 // of live tiles.
+#ifndef WCNS_REG_WAVES
+#define WCNS_REG_WAVES 5
+#endif
+constexpr int sweep_waves(int nv, int tmw, int spec) {
+  return spec == SPEC_GENERIC ? 1
+         : spec != SPEC_FE    ? 4
+         : sweep_reg(nv, tmw) ? WCNS_REG_WAVES
+                              : 6;
+}
+
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(SPEC == SPEC_GENERIC ? 1 : (SPEC == SPEC_FE ? 6 : 4))))
+    __attribute__((amdgpu_waves_per_eu(sweep_waves(NV, TM * W, SPEC))))
     sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g, int mode) {
   extern __shared__ double smem[];
   int64_t tile;
@@ -430,9 +501,7 @@ bool sweep_shape_ok(int nv, int dir, int tm, int w) {
   const bool known = (tm == 16 && w == 8) || (tm == 32 && w == 4) || (tm == 32 && w == 8) ||
                      (tm == 64 && w == 4) || (tm == 128 && w == 2) || (tm == 256 && w == 1);
   if (!known) return false;
-  const size_t nr = nv > 1 ? nv + 1 : 0;
-  const size_t lds = sizeof(double) * ((size_t)nv * (tm + 5) * w + (nr + 2 * nv) * (size_t)tm * w + 64);
-  return lds <= 64 * 1024;
+  return sizeof(double) * sweep_lds_doubles(nv, tm, w) <= 64 * 1024;
 }
 
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
