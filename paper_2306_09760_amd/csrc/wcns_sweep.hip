@@ -74,8 +74,29 @@ struct SweepLayout {
   static_assert((1 << LW) == W, "W must be a power of two up to 16");
 };
 
+// The sweep kernel's arguments, one struct so that its layout in the kernel
+// argument segment is the struct's.
+struct SweepKernArgs {
+  SweepArgs a;
+  BatchArgs b;
+  TileGeom g;
+  int mode;
+};
+using SweepKernArgsPtr = const __attribute__((address_space(4))) SweepKernArgs*;
+
+// The kernel's arguments for a late phase.  Values held in scalar registers
+// from the kernel's start through the interpolation spill to VGPR lanes
+// (every reload a VALU instruction per lane) once the FE constants fill the
+// scalar file; the empty asm hides that the segment does not change, so the
+// late phase reads what it needs with scalar loads at that point instead.
+__device__ __forceinline__ SweepKernArgsPtr sweep_kernargs_late() {
+  unsigned long long p = reinterpret_cast<unsigned long long>(__builtin_amdgcn_kernarg_segment_ptr());
+  asm volatile("" : "+s"(p));
+  return reinterpret_cast<SweepKernArgsPtr>(p);
+}
+
 // One tile (logical index `tile`) of a sweep; every lane of the workgroup
-// calls it.
+// calls it from sweep_kernel (its late phases re-read the kernel arguments).
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
 __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& b,
                                            const TileGeom& g, int mode, int64_t tile,
@@ -318,8 +339,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
   double oih = 0.0, odt = 0.0;
   if constexpr (BATCH) {
     if (onode >= 0) {
-      oih = b.ih[oprob];
-      if (mode == MODE_STAGE) odt = b.dtp[oprob];
+      const SweepKernArgsPtr k = sweep_kernargs_late();
+      oih = k->b.ih[oprob];
+      if (mode == MODE_STAGE) odt = k->b.dtp[oprob];
     }
   }
 
@@ -365,6 +387,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
   __syncthreads();
 
   // flux difference and output
+  const EmitArgs ea = emit_args(sweep_kernargs_late()->a);
   unsigned long long rbits = 0;  // wave rate of the lane's written node (SweepArgs::wmax)
 #pragma unroll 1
   for (int q = tid; q < TL * W; q += NT) {
@@ -415,13 +438,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
     }
     if constexpr (BATCH) {
       double y[NV];
-      emit_rt<NV>(mode, a, base + i * stride + c, a.npts, res, Un, dt, y);
+      emit_rt<NV>(mode, ea, base + i * stride + c, a.npts, res, Un, dt, y);
       if (a.wmax && mode == MODE_STAGE) {
         const double ihv[1] = {ih};
         rbits = __builtin_bit_cast(unsigned long long, wave_rate<1>(y, a.pp.gamma, ihv));
       }
     } else {
-      emit_rt<NV>(mode, a, base + i * stride + c, a.npts, res, Un, dt);
+      emit_rt<NV>(mode, ea, base + i * stride + c, a.npts, res, Un, dt);
     }
   }
   // The batch's last stage of a step also takes each problem's maximum wave
@@ -477,8 +500,12 @@ constexpr int sweep_waves(int nv, int tmw, int spec) {
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(sweep_waves(NV, TM * W, SPEC))))
-    sweep_kernel(SweepArgs a, BatchArgs b, TileGeom g, int mode) {
+    sweep_kernel(SweepKernArgs k) {
   extern __shared__ double smem[];
+  const SweepArgs& a = k.a;
+  const BatchArgs& b = k.b;
+  const TileGeom& g = k.g;
+  const int mode = k.mode;
   int64_t tile;
   if (BATCH && b.live) {
     const int n = *b.nlive;
@@ -507,8 +534,9 @@ bool sweep_shape_ok(int nv, int dir, int tm, int w) {
 template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
 static hipError_t sweep_launch(const SweepArgs& a, const BatchArgs& b, const TileGeom& g,
                                int mode, size_t lds, hipStream_t s) {
+  const SweepKernArgs k{a, b, g, mode};
   hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC, TM, W>), dim3((unsigned)g.ntiles),
-                     dim3(256), lds, s, a, b, g, mode);
+                     dim3(256), lds, s, k);
   return hipGetLastError();
 }
 

@@ -141,18 +141,48 @@ __device__ __forceinline__ void flag_status(int32_t* status) {
   if (status) atomicOr(status, 1);
 }
 
+// The fields of SweepArgs that writing a result needs (emit): a kernel may
+// read them late, from its argument segment, instead of holding them in
+// scalar registers through its main loop.
+struct EmitArgs {
+  const double* U0;
+  const double* Rin;
+  double* out;
+  int32_t* status;
+  double ca, cb, cr;
+  PhysParams pp;
+};
+
+template <class A>
+__device__ __forceinline__ EmitArgs emit_args(const A& a) {
+  EmitArgs e;
+  e.U0 = a.U0;
+  e.Rin = a.Rin;
+  e.out = a.out;
+  e.status = a.status;
+  e.ca = a.ca;
+  e.cb = a.cb;
+  e.cr = a.cr;
+  e.pp.gamma = a.pp.gamma;
+  e.pp.adv = a.pp.adv;
+  e.pp.charproj = a.pp.charproj;
+  return e;
+}
+
 // Writes one node's result according to the sweep mode (MODE_RES, MODE_ACC,
 // MODE_STAGE or MODE_LIN; `mode` is uniform, so the switch costs a scalar
-// branch).
-template <int NV>
-__device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gidx, int64_t vstride,
+// branch).  A is SweepArgs or EmitArgs.
+template <int NV, class A>
+__device__ __forceinline__ void emit_rt(int mode, const A& a, int64_t gidx, int64_t vstride,
                                         const double (&res)[NV], const double (&Un)[NV],
                                         double dt, double* yout = nullptr);
 
 // Writes one node's result according to the sweep mode.  Un is the state
-// under the stencil at that node (needed by the stage combine).
-template <int NV, int MODE>
-__device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t vstride,
+// under the stencil at that node (needed by the stage combine).  The stage
+// combines read every input value of the node before the arithmetic, so
+// that the loads are in flight together.
+template <int NV, int MODE, class A>
+__device__ __forceinline__ void emit(const A& a, int64_t gidx, int64_t vstride,
                                      const double (&res)[NV], const double (&Un)[NV],
                                      double dt, double* yout = nullptr) {
   if constexpr (MODE == MODE_RES) {
@@ -162,27 +192,39 @@ __device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t v
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = a.Rin[v * vstride + gidx] + res[v];
   } else if constexpr (MODE == MODE_LIN) {
-    double y[NV];
+    double y[NV], rin[NV], u0[NV];
+    const bool hr = a.Rin != nullptr, h0 = a.ca != 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      rin[v] = hr ? a.Rin[v * vstride + gidx] : 0.0;
+      u0[v] = h0 ? a.U0[v * vstride + gidx] : 0.0;
+    }
     const double crdt = a.cr * dt;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double r = res[v];
-      if (a.Rin) r += a.Rin[v * vstride + gidx];
+      if (hr) r += rin[v];
       double s = __builtin_fma(crdt, r, a.cb * Un[v]);
-      if (a.ca != 0.0) s = __builtin_fma(a.ca, a.U0[v * vstride + gidx], s);
+      if (h0) s = __builtin_fma(a.ca, u0[v], s);
       y[v] = s;
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = y[v];
     if (!physical<NV>(y, a.pp.gamma)) flag_status(a.status);
   } else {
-    double y[NV];
+    double y[NV], rin[NV], u0[NV];
+    const bool hr = a.Rin != nullptr, h0 = a.ca != 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      rin[v] = hr ? a.Rin[v * vstride + gidx] : 0.0;
+      u0[v] = h0 ? a.U0[v * vstride + gidx] : 0.0;
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       double r = res[v];
-      if (a.Rin) r += a.Rin[v * vstride + gidx];
+      if (hr) r += rin[v];
       double s = a.cb * __builtin_fma(dt, r, Un[v]);
-      if (a.ca != 0.0) s = __builtin_fma(a.ca, a.U0[v * vstride + gidx], s);
+      if (h0) s = __builtin_fma(a.ca, u0[v], s);
       y[v] = s;
     }
 #pragma unroll
@@ -195,8 +237,8 @@ __device__ __forceinline__ void emit(const SweepArgs& a, int64_t gidx, int64_t v
   }
 }
 
-template <int NV>
-__device__ __forceinline__ void emit_rt(int mode, const SweepArgs& a, int64_t gidx, int64_t vstride,
+template <int NV, class A>
+__device__ __forceinline__ void emit_rt(int mode, const A& a, int64_t gidx, int64_t vstride,
                                         const double (&res)[NV], const double (&Un)[NV],
                                         double dt, double* yout) {
   if (mode == MODE_RES)
