@@ -155,7 +155,12 @@ void interp_params(const wcns_desc* d, InterpParams* ip) {
         b += softplus(2.0 * d->xi * ((m == i ? 1.0 : 0.0) - nu[first[m] + j]));
     B = std::max(B, b);
   }
-  ip->fast_fe = (ip->shared_exp && B < 600.0) ? 1 : 0;
+  // The fast path also takes the third map's exponential as
+  // Ke / (E_0 E_1): E_0 E_1 = exp(2 xi (w_0 + w_1 - c_0 - c_1)) must stay a
+  // normal number for w_0 + w_1 in [0, 1].
+  const bool prod_ok = 2.0 * d->xi < 650.0 && 2.0 * d->xi * (c[0] + c[1]) < 650.0 &&
+                       std::fabs(2.0 * d->xi * (1.0 - c[0] - c[1] - c[2])) < 650.0;
+  ip->fast_fe = (ip->shared_exp && B < 600.0 && prod_ok) ? 1 : 0;
   for (int m = 0; m < 3; ++m) {
     ip->C2[m] = ip->shared_exp ? 2.0 * d->xi * c[m] : 0.0;
     for (int j = 0; j < count[m]; ++j) {
@@ -163,6 +168,7 @@ void interp_params(const wcns_desc* d, InterpParams* ip) {
       ip->K[k] = ip->shared_exp ? std::exp(2.0 * d->xi * (c[m] - nu[k])) : nu[k];
     }
   }
+  ip->Ke = ip->shared_exp ? std::exp(2.0 * d->xi - ip->C2[0] - ip->C2[1] - ip->C2[2]) : 0.0;
 }
 
 int device_cus() {

@@ -54,6 +54,7 @@ struct InterpParams {
   //   shared_exp = 0:  K[j] = nu_j                      (C2 unused)
   double K[10];
   double C2[3];
+  double Ke;        // exp(2 xi - C2[0] - C2[1] - C2[2]) (shared_exp; fe_map_frac)
   int weights;      // WJS .. WLIN
   int zpow;         // exponent p of eq. 14 (1..4)
   int shared_exp;   // 1: one exponential per map (xi * max|nu - c| < 300)
@@ -275,13 +276,12 @@ __device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double*
 // (469 at xi = 100, kappa = 0.5).  The host selects this path only while
 // B < 600 (fast_fe), which leaves e^100 of headroom for the candidate values
 // that multiply the products; below e^-45 a q_j rounds away against 1.
-template <int NT, bool TAB>
-__device__ __forceinline__ double fe_map_frac(double w, const double (&a)[NT],
-                                              const double (&b)[NT], const double* K, double C2,
-                                              double xi2, const double* xt, double* den) {
+// E = exp(2 xi w - C2) is the caller's (weigh5).
+template <int NT>
+__device__ __forceinline__ double fe_map_frac(double w, double E, const double (&a)[NT],
+                                              const double (&b)[NT], const double* K,
+                                              double* den) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
-  const double z = __builtin_fma(xi2, w, -C2);
-  const double E = TAB ? exp_tab(z, xt) : exp_cw(z);
   double D[NT], A[NT];  // A holds -2 A_j
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
@@ -343,12 +343,22 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     const double z2 = FAM::d2 * (q2 + t2) * (q0 * q1);
     const double zi = rcp(z0 + z1 + z2);
     const double xi2 = 2.0 * P.xi;
+    const double w0 = z0 * zi, w1 = z1 * zi, w2 = z2 * zi;
+    // E_k = exp(2 xi w_k - C2_k).  The Z weights sum to one, so E_0 E_1 E_2 =
+    // exp(2 xi - C2_0 - C2_1 - C2_2) = Ke and the third exponential is
+    // Ke / (E_0 E_1); E_0 E_1 lies within [e^(-2 xi (c_0 + c_1)),
+    // e^(2 xi (1 - c_0 - c_1))], normal numbers wherever the host selects
+    // this path (fast_fe).
+    const double zE0 = __builtin_fma(xi2, w0, -P.C2[0]), zE1 = __builtin_fma(xi2, w1, -P.C2[1]);
+    const double E0 = TAB ? exp_tab(zE0, xt) : exp_cw(zE0);
+    const double E1 = TAB ? exp_tab(zE1, xt) : exp_cw(zE1);
+    const double E2 = P.Ke * rcp(E0 * E1);
     // g_k = n_k / e_k; the normalised weights g_k / sum_l g_l over the
     // common denominator e_0 e_1 e_2 (below e^B, fe_map_frac): one reciprocal.
     double e0, e1, e2;
-    const double n0 = fe_map_frac<3, TAB>(z0 * zi, FAM::m0a, FAM::m0b, P.K, P.C2[0], xi2, xt, &e0);
-    const double n1 = fe_map_frac<4, TAB>(z1 * zi, FAM::m1a, FAM::m1b, P.K + 3, P.C2[1], xi2, xt, &e1);
-    const double n2 = fe_map_frac<3, TAB>(z2 * zi, FAM::m2a, FAM::m2b, P.K + 7, P.C2[2], xi2, xt, &e2);
+    const double n0 = fe_map_frac<3>(w0, E0, FAM::m0a, FAM::m0b, P.K, &e0);
+    const double n1 = fe_map_frac<4>(w1, E1, FAM::m1a, FAM::m1b, P.K + 3, &e1);
+    const double n2 = fe_map_frac<3>(w2, E2, FAM::m2a, FAM::m2b, P.K + 7, &e2);
     // T_k = n_k prod_{l != k} e_l: T_0 = A e_2, T_1 = B e_2, T_2 = C
     const double A = n0 * e1, B = n1 * e0, C = n2 * (e0 * e1);
     const double num = __builtin_fma(e2, __builtin_fma(A, c0, B * c1), C * c2);
