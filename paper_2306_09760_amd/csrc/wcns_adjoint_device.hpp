@@ -45,12 +45,16 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
   const double zi = rcp(Z0 + Z1 + Z2);
   const double z[3] = {Z0 * zi, Z1 * zi, Z2 * zi};
   const double xi2 = 2.0 * P.xi, xi4 = 4.0 * P.xi;
+  // E_k = exp(2 xi z_k - C2_k); the third from the other two as in weigh5
+  // (the z_k sum to one: E_0 E_1 E_2 = Ke)
+  const double zE0 = __builtin_fma(xi2, z[0], -P.C2[0]), zE1 = __builtin_fma(xi2, z[1], -P.C2[1]);
+  const double E0 = TAB ? exp_tab(zE0, xt) : exp_cw(zE0);
+  const double E1 = TAB ? exp_tab(zE1, xt) : exp_cw(zE1);
+  const double E2 = P.Ke * rcp(E0 * E1);
   double g[3], gp[3];
-  auto map = [&](auto ntc, int k, const double* av, const double* bv, const double* K, double C2) {
+  auto map = [&](auto ntc, int k, const double* av, const double* bv, const double* K, double E) {
     constexpr int NT = decltype(ntc)::value;
     const double w = z[k];
-    const double E = TAB ? exp_tab(__builtin_fma(xi2, w, -C2), xt)
-                         : exp_cw(__builtin_fma(xi2, w, -C2));
     double D[NT], o[NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) D[j] = __builtin_fma(E, K[j], 1.0);
@@ -82,9 +86,9 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
     g[k] = gk;
     gp[k] = dk;
   };
-  map(std::integral_constant<int, 3>{}, 0, kG0a, kG0b, P.K, P.C2[0]);
-  map(std::integral_constant<int, 4>{}, 1, kG1a, kG1b, P.K + 3, P.C2[1]);
-  map(std::integral_constant<int, 3>{}, 2, kG2a, kG2b, P.K + 7, P.C2[2]);
+  map(std::integral_constant<int, 3>{}, 0, kG0a, kG0b, P.K, E0);
+  map(std::integral_constant<int, 4>{}, 1, kG1a, kG1b, P.K + 3, E1);
+  map(std::integral_constant<int, 3>{}, 2, kG2a, kG2b, P.K + 7, E2);
   const double rg = rcp(g[0] + g[1] + g[2]);
   const double w0 = g[0] * rg, w1 = g[1] * rg, w2 = g[2] * rg;
   c0b = w0 * yb;
