@@ -337,10 +337,11 @@ def main():
 
     # ---- the whole run to t = 0.2 ----------------------------------------
     # rk3_steps calls of 256 steps with a host check of completion after
-    # each (what a caller running to the end does), timed with HIP events;
-    # then an untimed replay counts each problem's live steps on the device
-    # (single steps give bitwise the times of the fused call), which gives the
-    # exact number of grid-point stage updates.
+    # each (what a caller running to the end does), each call's stage
+    # launches sized to the live-tile count read at the previous check,
+    # timed with HIP events; then an untimed replay counts each problem's
+    # live steps on the device (single steps give bitwise the times of the
+    # fused call), which gives the exact number of grid-point stage updates.
     whole = None
     if not args.no_whole_run:
         reset(t)
@@ -350,11 +351,13 @@ def main():
         rwall0 = time.perf_counter()
         r0.record()
         issued = 0
+        live = None
         while True:
-            B.rk3_steps(U, t, T_END, 0.5, chunk, status)
+            B.rk3_steps(U, t, T_END, 0.5, chunk, status, max_live=live)
             issued += chunk
             if bool((t >= T_END).all().item()):
                 break
+            live = max(1, B.live_tiles())
         r1.record()
         torch.cuda.synchronize()
         run_ms = r0.elapsed_time(r1)
@@ -376,8 +379,9 @@ def main():
                  "fraction_of_k_step_rate": (run_pts / (run_ms * 1e-3)) / value,
                  "status_word": run_bad,
                  "note": "every problem to t = 0.2 by rk3_steps calls of 256 steps, a host "
-                         "check of completion after each; updates counted per problem over "
-                         "its live steps"}
+                         "check of completion after each, the stage launches of each call "
+                         "sized to the live tiles at the previous check; updates counted per "
+                         "problem over its live steps"}
 
     # ---- dominant kernel: the batch stage kernel --------------------------
     # stage 2 (out = 3/4 U^n + 1/4 (U^(1) + dt R(U^(1)))) with U^(1), U^n and

@@ -272,6 +272,29 @@ wcns_status wcns_batch_rk3_steps(wcns_batch_plan* plan, double* U, void* work, d
                                  double t_end, double cfl, int32_t nsteps, int32_t* status_dev,
                                  void* stream);
 
+/* The length of the live-tile list in `work` (the tiles of the problems
+   with dt_p > 0 at the last rebuild), copied to the host *count: blocks
+   until the work on `stream` is done.  WCNS_EINVAL if `work` holds no list
+   for the plan's current tile size (no wcns_batch_cfl, wcns_batch_rk3_step
+   or wcns_batch_rk3_steps on it since the last tile change). */
+wcns_status wcns_batch_live_tiles(const wcns_batch_plan* plan, const void* work, int32_t* count,
+                                  void* stream);
+
+/* wcns_batch_rk3_steps with every stage launch sized to max_live
+   workgroups instead of one per tile: near the end of a run, when few
+   problems are live, the full-size launches spend most of their time on
+   workgroups that only read the list's length and leave (4096 tubes of
+   256-4096 nodes: ~35 000 tiles, ~20 us per step of such launches).  The caller
+   bounds the list: within one run towards a fixed t_end problems only
+   finish, so a count from wcns_batch_live_tiles, taken after any earlier
+   step of that run, bounds every later list.  A launch whose list is
+   longer than max_live sets bit 1 (value 2) of *status_dev (required
+   here) and leaves tiles out of that stage.  WCNS_EINVAL for max_live < 1
+   or a NULL status_dev, else as wcns_batch_rk3_steps. */
+wcns_status wcns_batch_rk3_steps_capped(wcns_batch_plan* plan, double* U, void* work,
+                                        double* t_dev, double t_end, double cfl, int32_t nsteps,
+                                        int32_t* status_dev, int32_t max_live, void* stream);
+
 /* The two kernels of wcns_batch_rk3_step, for callers composing their own
    step.  wcns_batch_cfl: per-problem dt_p (as above) into the workspace and
    t_dev[p] += dt_p.  wcns_batch_stage: SSP-RK3 stage `stage` (1, 2 or 3) of

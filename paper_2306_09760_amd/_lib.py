@@ -34,6 +34,7 @@ EXPORTS = [
     "wcns_plan_get_tiles", "wcns_plan_set_tiles", "wcns_batch_plan_create",
     "wcns_batch_plan_destroy", "wcns_batch_state_elems", "wcns_batch_workspace_bytes",
     "wcns_batch_residual", "wcns_batch_rk3_step", "wcns_batch_rk3_steps", "wcns_batch_set_graph", "wcns_batch_last_dt",
+    "wcns_batch_live_tiles", "wcns_batch_rk3_steps_capped",
     "wcns_batch_autotune", "wcns_batch_get_tile", "wcns_batch_set_tile",
     "wcns_batch_cfl", "wcns_batch_stage", "wcns_probe_fp64_fma", "wcns_probe_copy",
     "wcns_status_string", "wcns_last_error",
@@ -98,6 +99,9 @@ def lib():
         "wcns_batch_rk3_steps": (st, [vp, vp, vp, vp, C.c_double, C.c_double, C.c_int32, vp, vp]),
         "wcns_batch_set_graph": (st, [vp, C.c_int32]),
         "wcns_batch_last_dt": (st, [vp, vp, vp, vp]),
+        "wcns_batch_live_tiles": (st, [vp, vp, vp, vp]),
+        "wcns_batch_rk3_steps_capped": (st, [vp, vp, vp, vp, C.c_double, C.c_double, C.c_int32, vp,
+                                             C.c_int32, vp]),
         "wcns_batch_cfl": (st, [vp, vp, vp, vp, C.c_double, C.c_double, vp]),
         "wcns_batch_stage": (st, [vp, C.c_int32, vp, vp, vp, vp, vp, vp]),
         "wcns_batch_autotune": (st, [vp, vp, vp, vp]),

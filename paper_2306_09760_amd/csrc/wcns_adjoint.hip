@@ -486,8 +486,10 @@ __global__ void __launch_bounds__(256)
 // --------------------------------------------------------------- launchers --
 static inline int64_t ceil_div64(int64_t x, int64_t y) { return (x + y - 1) / y; }
 
-// Tile shape per variable count: 128 midpoints per tile while the LDS stays
-// within 64 KB, 64 for the 3D Euler system.  y and z tiles are two columns
+// Tile shape per variable count: 128 midpoints per tile for the scalar
+// equation and the 1D Euler system, 64 for the 2D and 3D Euler systems (LDS
+// per tile 33 KB and 41 KB: four and three tiles per CU; the 2D residual
+// adjoint at 1024^2 measured faster with 64 than with 128).  y and z tiles are two columns
 // wide: a taller tile recomputes fewer overlap rows (5 of 64 instead of 5
 // of 32 with four columns), and the XCD-aware order keeps the column pairs
 // that share a cache line on one L2 (2D 1024^2 residual adjoint: 2 % faster
@@ -510,7 +512,7 @@ static hipError_t adj_go(const AdjArgs& a, hipStream_t s) {
   constexpr int TM = AdjShape<NV, DIR>::TM, W = AdjShape<NV, DIR>::W;
   using L = AdjLayout<NV, TM, W>;
   static_assert(L::lds_doubles * sizeof(double) <= 160 * 1024, "adjoint tile exceeds 160 KB of LDS");
-  TileGeom g;
+  TileGeom g{};
   g.tm = TM;
   g.w = W;
   g.lw = L::LW;

@@ -994,7 +994,7 @@ wcns_status wcns_batch_residual(wcns_batch_plan* B, const double* U, double* R, 
 static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work, double* t_dev,
                                       double t_end, double cfl, int32_t* status, hipStream_t s,
                                       bool fused_dt = false, bool keep_max = false,
-                                      bool rebuild = true) {
+                                      bool rebuild = true, int32_t cap = 0) {
   char* w = (char*)work;
   double* W1 = (double*)(w + B->off_W1);
   double* W2 = (double*)(w + B->off_W2);
@@ -1026,7 +1026,7 @@ static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work,
     a.ca = ca[k];
     a.cb = cb[k];
     a.wmax = (k == 2 && keep_max) ? wmax : nullptr;
-    WCNS_HIP(launch_batch_sweep(a, b, MODE_STAGE, B->tm, s), "batch stage launch");
+    WCNS_HIP(launch_batch_sweep(a, b, MODE_STAGE, B->tm, s, cap), "batch stage launch");
   }
   return WCNS_OK;
 }
@@ -1036,10 +1036,9 @@ static wcns_status batch_step_enqueue(wcns_batch_plan* B, double* U, void* work,
 // finished stay listed and leave at once.
 static const int32_t kLiveEvery = 4;
 
-wcns_status wcns_batch_rk3_steps(wcns_batch_plan* B, double* U, void* work, double* t_dev,
-                                 double t_end, double cfl, int32_t nsteps, int32_t* status_dev,
-                                 void* stream) {
-  g_err.clear();
+static wcns_status batch_rk3_steps(wcns_batch_plan* B, double* U, void* work, double* t_dev,
+                                   double t_end, double cfl, int32_t nsteps, int32_t* status_dev,
+                                   int32_t cap, void* stream) {
   if (!B || !U || !work || !t_dev) return fail(WCNS_EINVAL, "NULL argument");
   if (!(cfl > 0.0)) return fail(WCNS_EINVAL, "cfl must be > 0");
   if (!std::isfinite(t_end)) return fail(WCNS_EINVAL, "t_end must be finite");
@@ -1047,9 +1046,39 @@ wcns_status wcns_batch_rk3_steps(wcns_batch_plan* B, double* U, void* work, doub
   hipStream_t s = (hipStream_t)stream;
   for (int32_t k = 0; k < nsteps; ++k) {
     const wcns_status st = batch_step_enqueue(B, U, work, t_dev, t_end, cfl, status_dev, s, k > 0,
-                                              k + 1 < nsteps, k % kLiveEvery == 0);
+                                              k + 1 < nsteps, k % kLiveEvery == 0, cap);
     if (st != WCNS_OK) return st;
   }
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_rk3_steps(wcns_batch_plan* B, double* U, void* work, double* t_dev,
+                                 double t_end, double cfl, int32_t nsteps, int32_t* status_dev,
+                                 void* stream) {
+  g_err.clear();
+  return batch_rk3_steps(B, U, work, t_dev, t_end, cfl, nsteps, status_dev, 0, stream);
+}
+
+wcns_status wcns_batch_rk3_steps_capped(wcns_batch_plan* B, double* U, void* work, double* t_dev,
+                                        double t_end, double cfl, int32_t nsteps,
+                                        int32_t* status_dev, int32_t max_live, void* stream) {
+  g_err.clear();
+  if (!status_dev) return fail(WCNS_EINVAL, "a capped call needs status_dev");
+  if (max_live < 1) return fail(WCNS_EINVAL, "max_live %d < 1", max_live);
+  return batch_rk3_steps(B, U, work, t_dev, t_end, cfl, nsteps, status_dev, max_live, stream);
+}
+
+wcns_status wcns_batch_live_tiles(const wcns_batch_plan* B, const void* work, int32_t* count,
+                                  void* stream) {
+  g_err.clear();
+  if (!B || !work || !count) return fail(WCNS_EINVAL, "NULL argument");
+  if (B->list_work != work || B->list_tm != B->tm)
+    return fail(WCNS_EINVAL, "no live-tile list in this workspace for the current tile size");
+  hipStream_t s = (hipStream_t)stream;
+  WCNS_HIP(hipMemcpyAsync(count, (const char*)work + B->off_nlive, sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s),
+           "live count copy");
+  WCNS_HIP(hipStreamSynchronize(s), "live count sync");
   return WCNS_OK;
 }
 

@@ -73,6 +73,7 @@ struct TileGeom {
   // of equal problems (line r at slots [r L, (r+1) L), L = n[0] + 2G)
   int64_t lines;
   double inv_line;       // 1 / L
+  int64_t grid;          // workgroups launched (0: ntiles)
 };
 
 // Launchers.  All enqueue on `stream` and return the hipError_t of the launch
@@ -80,8 +81,10 @@ struct TileGeom {
 bool sweep_shape_ok(int nv, int dir, int tm, int w);
 hipError_t launch_sweep(int nv, int dir, const SweepArgs& a, int mode, int tm, int w,
                         hipStream_t stream);
+// cap > 0 (with a live list in b): launch min(cap, b.ntiles) workgroups,
+// the caller's bound on the list's length (see wcns_batch_rk3_steps_capped).
 hipError_t launch_batch_sweep(const SweepArgs& a, const BatchArgs& b, int mode, int tm,
-                              hipStream_t stream);
+                              hipStream_t stream, int32_t cap = 0);
 hipError_t launch_cfl(int nv, int ndim, const double* U, int64_t npts, double gamma,
                       const double* ih, const double* adv, double cfl, double* partial,
                       int nblocks, double* dt_out, hipStream_t stream);

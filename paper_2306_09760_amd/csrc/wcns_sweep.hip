@@ -509,6 +509,9 @@ __global__ void __launch_bounds__(256)
   int64_t tile;
   if (BATCH && b.live) {
     const int n = *b.nlive;
+    // a launch capped below the list's length leaves tiles out: say so
+    if (n > (int)gridDim.x && blockIdx.x == 0 && threadIdx.x == 0 && a.status)
+      atomicOr(a.status, 2);
     if ((int)blockIdx.x >= n) return;
     tile = b.live[xcd_tile(blockIdx.x, n)];
   } else {
@@ -535,8 +538,8 @@ template <int NV, int DIR, bool BATCH, int SPEC, int TM, int W>
 static hipError_t sweep_launch(const SweepArgs& a, const BatchArgs& b, const TileGeom& g,
                                int mode, size_t lds, hipStream_t s) {
   const SweepKernArgs k{a, b, g, mode};
-  hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC, TM, W>), dim3((unsigned)g.ntiles),
-                     dim3(256), lds, s, k);
+  hipLaunchKernelGGL((sweep_kernel<NV, DIR, BATCH, SPEC, TM, W>),
+                     dim3((unsigned)(g.grid > 0 ? g.grid : g.ntiles)), dim3(256), lds, s, k);
   return hipGetLastError();
 }
 
@@ -568,7 +571,7 @@ static hipError_t sweep_shape(const SweepArgs& a, const BatchArgs& b, const Tile
 }
 
 static TileGeom make_geom(int dir, const int64_t n[3], int diff, int tm, int w) {
-  TileGeom g;
+  TileGeom g{};
   g.tm = tm;
   g.w = w;
   g.lw = 0;
@@ -580,6 +583,7 @@ static TileGeom make_geom(int dir, const int64_t n[3], int diff, int tm, int w) 
   g.ntiles = g.segs * g.xgroups * others;
   g.lines = 0;
   g.inv_line = 0.0;
+  g.grid = 0;
   if (dir == 0) {  // packed x-lines
     const int64_t L = n[0] + 2 * (diff ? 5 : 4);
     g.lines = others;
@@ -606,9 +610,9 @@ hipError_t launch_sweep(int nv, int dir, const SweepArgs& a, int mode, int tm, i
 }
 
 hipError_t launch_batch_sweep(const SweepArgs& a, const BatchArgs& b, int mode, int tm,
-                              hipStream_t stream) {
+                              hipStream_t stream, int32_t cap) {
   if (!sweep_shape_ok(3, 0, tm, 1)) return hipErrorInvalidConfiguration;
-  TileGeom g;
+  TileGeom g{};
   g.tm = tm;
   g.w = 1;
   g.lw = 0;
@@ -619,6 +623,7 @@ hipError_t launch_batch_sweep(const SweepArgs& a, const BatchArgs& b, int mode, 
   g.ntiles = b.ntiles;
   g.lines = 0;
   g.inv_line = 0.0;
+  g.grid = (cap > 0 && b.live && cap < b.ntiles) ? cap : 0;
   return sweep_shape<3, 0, true>(a, b, g, mode, stream);
 }
 

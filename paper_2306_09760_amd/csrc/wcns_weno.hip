@@ -242,7 +242,7 @@ template <int NV, int DIR, int TM, int W>
 static hipError_t weno_go(const SweepArgs& a, int mode, hipStream_t s) {
   using L = WenoLayout<NV, TM, W>;
   static_assert(L::lds_doubles * sizeof(double) <= 64 * 1024, "WENO tile exceeds 64 KB of LDS");
-  TileGeom g;
+  TileGeom g{};
   g.tm = TM;
   g.w = W;
   g.lw = L::LW;

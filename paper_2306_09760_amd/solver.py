@@ -297,16 +297,34 @@ class BatchPlan:
                                         float(cfl), _ptr(status), _stream()), "wcns_batch_rk3_step")
         return U
 
-    def rk3_steps(self, U, t, t_end, cfl=0.5, nsteps=1, status=None):
+    def rk3_steps(self, U, t, t_end, cfl=0.5, nsteps=1, status=None, max_live=None):
         """nsteps rk3_step calls in one: each step's CFL maximum is taken by
-        the previous step's last stage (see include/wcns.h)."""
+        the previous step's last stage (see include/wcns.h).  max_live: a
+        bound on the live-tile list for the whole call (live_tiles() after an
+        earlier step of the same run to the same t_end); the stage launches
+        are sized to it (status required; bit 1 set if the bound was too
+        small)."""
         self._check_state(U)
         self._t(t)
         self._status(status)
-        check(lib().wcns_batch_rk3_steps(self._h, _ptr(U), _ptr(self.work), _ptr(t), float(t_end),
-                                         float(cfl), int(nsteps), _ptr(status), _stream()),
-              "wcns_batch_rk3_steps")
+        if max_live is None:
+            check(lib().wcns_batch_rk3_steps(self._h, _ptr(U), _ptr(self.work), _ptr(t),
+                                             float(t_end), float(cfl), int(nsteps), _ptr(status),
+                                             _stream()), "wcns_batch_rk3_steps")
+        else:
+            check(lib().wcns_batch_rk3_steps_capped(self._h, _ptr(U), _ptr(self.work), _ptr(t),
+                                                    float(t_end), float(cfl), int(nsteps),
+                                                    _ptr(status), int(max_live), _stream()),
+                  "wcns_batch_rk3_steps_capped")
         return U
+
+    def live_tiles(self):
+        """Length of the live-tile list the last step built (synchronises the
+        current stream)."""
+        n = C.c_int32(0)
+        check(lib().wcns_batch_live_tiles(self._h, _ptr(self.work), C.addressof(n), _stream()),
+              "wcns_batch_live_tiles")
+        return int(n.value)
 
     def cfl(self, U, t, t_end, cfl=0.5):
         """Per-problem dt into the workspace; t += dt (first kernel of a step)."""
@@ -363,17 +381,23 @@ class BatchPlan:
         self._status(status)
         t = torch.zeros(self.nprob, dtype=torch.float64, device=self.device)
         steps = 0
+        live = None  # bound on the live-tile list, from the last check (fused calls)
         while steps < max_steps:
             if fused:
-                self.rk3_steps(U, t, t_end, cfl, check_every, status)
+                self.rk3_steps(U, t, t_end, cfl, check_every, status, max_live=live)
             else:
                 for _ in range(check_every):
                     self.rk3_step(U, t, t_end, cfl, status)
             steps += check_every
-            if int(status.item()) & 1:
+            word = int(status.item())
+            if word & 1:
                 bad = torch.nonzero(t < t_end).flatten().tolist()
                 raise _lib.WCNSError(f"non-physical state after {steps} steps (problems not at "
                                      f"t_end: {bad[:16]}{' ...' if len(bad) > 16 else ''})")
+            if word:
+                raise _lib.WCNSError(f"status word {word} after {steps} steps")
             if bool((t >= t_end).all().item()):
                 break
+            if fused:
+                live = max(1, self.live_tiles())
         return t, steps

@@ -197,3 +197,16 @@ def test_noalloc_step_refuses_plans_beyond_its_array_on_host(L):
         assert lib.wcns_rk3_step_noalloc(h, None, None, 0.5, None, None) == L.WCNS_EINVAL
     finally:
         lib.wcns_plan_destroy(h)
+
+
+def test_capped_batch_steps_refuse_on_host(L):
+    """wcns_batch_rk3_steps_capped needs a status word and max_live >= 1;
+    wcns_batch_live_tiles refuses NULL arguments (no device work)."""
+    lib = L.lib()
+    x = C.c_void_p(16)
+    n = C.c_int32(0)
+    steps = lib.wcns_batch_rk3_steps_capped
+    assert steps(None, x, x, x, 0.2, 0.5, 4, None, 8, None) == L.WCNS_EINVAL    # no status
+    assert steps(None, x, x, x, 0.2, 0.5, 4, x, 0, None) == L.WCNS_EINVAL       # max_live 0
+    assert steps(None, x, x, x, 0.2, 0.5, 4, x, 8, None) == L.WCNS_EINVAL       # no plan
+    assert lib.wcns_batch_live_tiles(None, x, C.addressof(n), None) == L.WCNS_EINVAL

@@ -406,6 +406,49 @@ def test_rk3_steps_equal_single_steps(lib, W, nmin, nmax, tile):
         assert np.array_equal(ua, ub)
 
 
+@pytest.mark.parametrize("tile", [128, 256])
+def test_capped_steps_equal_uncapped(lib, W, tile):
+    """rk3_steps with the stage launches sized to the live-tile count read
+    after the previous call (problems finish between the calls) gives
+    bitwise the states and times of the uncapped calls; a bound below the
+    live count is reported in bit 1 of the status word."""
+    prob, U, meta = _small_batch(W, seed=8, nprob=48, nmin=60, nmax=900)
+    say("capped rk3_steps", tile)
+    t_end = 0.02  # the shortest tubes finish within the first calls, the longest later
+    res, counts = [], []
+    for capped in (False, True):
+        B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+        B.tile = tile
+        Ud = to_dev(U)
+        t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+        status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        out, live = [], None
+        for chunk in (4, 8, 16, 40, 60):
+            B.rk3_steps(Ud, t, t_end, 0.5, chunk, status, max_live=live if capped else None)
+            out.append((to_host(Ud).copy(), t.cpu().numpy().copy()))
+            if capped:
+                live = max(1, B.live_tiles())
+                counts.append(live)
+        assert int(status.item()) == 0
+        res.append(out)
+    assert counts[0] > counts[-1] >= 1  # problems finished between the calls
+    assert (res[0][-1][1] >= t_end).any()
+    for (ua, ta), (ub, tb) in zip(*res):
+        assert np.array_equal(ta, tb)
+        assert np.array_equal(ua, ub)
+    # a bound below the list's length: flagged
+    B = lib.BatchPlan(meta["offsets"], meta["h"], weights="fe", xi=100.0)
+    B.tile = tile
+    Ud = to_dev(U)
+    t = torch.zeros(B.nprob, dtype=torch.float64, device="cuda")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    B.rk3_steps(Ud, t, t_end, 0.5, 1, status)
+    n = B.live_tiles()
+    assert n > 1
+    B.rk3_steps(Ud, t, t_end, 0.5, 2, status, max_live=n - 1)
+    assert int(status.item()) & 2
+
+
 def test_finished_problems_are_untouched(lib, ora, W):
     """A finished problem shares its tiles with live neighbours (tiles are
     packed across problem ends): it stays bitwise unchanged, they advance one
