@@ -311,6 +311,7 @@ __device__ __forceinline__ double fe_map_frac(double w, double E, const double (
 // eq. 5, 1/6 for the WENO5 ones).
 struct FamWcns {
   static constexpr double d0 = D0, d1 = D1, d2 = D2, scale = 0.125;
+  static constexpr double dr1 = 10.0, dr2 = 5.0;  // d_1 / d_0, d_2 / d_0
   static constexpr const double (&m0a)[3] = kG0a;
   static constexpr const double (&m0b)[3] = kG0b;
   static constexpr const double (&m1a)[4] = kG1a;
@@ -332,15 +333,16 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
   constexpr bool FE = (SPEC == SPEC_FE);
   if constexpr (FE) {
     // Z weights (p = 2) over the common denominator: alpha_k b_0^2 b_1^2 b_2^2
-    // = d_k (b_k^2 + tau^2) times the other two squares; one reciprocal
-    // normalises them.  The smallest product, eps^6 = 1e-240, is still a
-    // normal number.
+    // = d_k (b_k^2 + tau^2) times the other two squares, here divided by d_0
+    // (the ratios d_k / d_0 are small integers; the normalisation removes
+    // the common factor); one reciprocal normalises them.  The smallest
+    // product, eps^6 = 1e-240, is still a normal number.
     const double tau = __builtin_fabs(b0 - b2);
     const double t2 = tau * tau;
     const double q0 = b0 * b0, q1 = b1 * b1, q2 = b2 * b2;
-    const double z0 = FAM::d0 * (q0 + t2) * (q1 * q2);
-    const double z1 = FAM::d1 * (q1 + t2) * (q0 * q2);
-    const double z2 = FAM::d2 * (q2 + t2) * (q0 * q1);
+    const double z0 = (q0 + t2) * (q1 * q2);
+    const double z1 = FAM::dr1 * (q1 + t2) * (q0 * q2);
+    const double z2 = FAM::dr2 * (q2 + t2) * (q0 * q1);
     const double zi = rcp(z0 + z1 + z2);
     const double xi2 = 2.0 * P.xi;
     const double w0 = z0 * zi, w1 = z1 * zi, w2 = z2 * zi;
@@ -350,15 +352,15 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     // e^(2 xi (1 - c_0 - c_1))], normal numbers wherever the host selects
     // this path (fast_fe).
     const double zE0 = __builtin_fma(xi2, w0, -P.C2[0]), zE1 = __builtin_fma(xi2, w1, -P.C2[1]);
-    const double E0 = TAB ? exp_tab(zE0, xt) : exp_cw(zE0);
-    const double E1 = TAB ? exp_tab(zE1, xt) : exp_cw(zE1);
-    const double E2 = P.Ke * rcp(E0 * E1);
+    const double Ex0 = TAB ? exp_tab(zE0, xt) : exp_cw(zE0);
+    const double Ex1 = TAB ? exp_tab(zE1, xt) : exp_cw(zE1);
+    const double Ex2 = P.Ke * rcp(Ex0 * Ex1);
     // g_k = n_k / e_k; the normalised weights g_k / sum_l g_l over the
     // common denominator e_0 e_1 e_2 (below e^B, fe_map_frac): one reciprocal.
     double e0, e1, e2;
-    const double n0 = fe_map_frac<3>(w0, E0, FAM::m0a, FAM::m0b, P.K, &e0);
-    const double n1 = fe_map_frac<4>(w1, E1, FAM::m1a, FAM::m1b, P.K + 3, &e1);
-    const double n2 = fe_map_frac<3>(w2, E2, FAM::m2a, FAM::m2b, P.K + 7, &e2);
+    const double n0 = fe_map_frac<3>(w0, Ex0, FAM::m0a, FAM::m0b, P.K, &e0);
+    const double n1 = fe_map_frac<4>(w1, Ex1, FAM::m1a, FAM::m1b, P.K + 3, &e1);
+    const double n2 = fe_map_frac<3>(w2, Ex2, FAM::m2a, FAM::m2b, P.K + 7, &e2);
     // T_k = n_k prod_{l != k} e_l: T_0 = A e_2, T_1 = B e_2, T_2 = C
     const double A = n0 * e1, B = n1 * e0, C = n2 * (e0 * e1);
     const double num = __builtin_fma(e2, __builtin_fma(A, c0, B * c1), C * c2);
@@ -475,6 +477,7 @@ static_assert(map_sums_vanish(kV0a, kV0b, 3) && map_sums_vanish(kV1a, kV1b, 4) &
 
 struct FamWeno {
   static constexpr double d0 = E0, d1 = E1, d2 = E2, scale = 1.0 / 6.0;
+  static constexpr double dr1 = 6.0, dr2 = 3.0;  // d_1 / d_0, d_2 / d_0
   static constexpr const double (&m0a)[3] = kV0a;
   static constexpr const double (&m0b)[3] = kV0b;
   static constexpr const double (&m1a)[4] = kV1a;

@@ -27,7 +27,8 @@
 // load | roe and flux | diff are synchronised.
 // LDS (doubles): sU[NV][TM+5][W] | sR[NR][TM*W] | sW[2 NV][TM*W] | the
 // 64-entry exp table; the flux overwrites sW rows 0..NV-1 (each task reads
-// its midpoint's two states before writing that midpoint's flux).  On the
+// its midpoint's two states before writing that midpoint's flux), and with
+// MND6 rows NV..2NV-1 with the physical flux of node m + 2.  On the
 // register path (sweep_reg: 4 and 5 variables, TM*W = 256) each lane keeps
 // its midpoint's Roe state in registers and sR is left out.
 #include <hip/hip_runtime.h>
@@ -383,6 +384,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) sW[v * TMW + q] = F[v];
+    if (a.diff == 0) {
+      // the physical flux of node m + 2 (q = m W + c) for the MND6
+      // difference, into the right-state rows this lane has just read: each
+      // node's flux is computed once instead of by both its neighbours
+      double Uc[NV], Fc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Uc[v] = sU[v * SV + q + 2 * W];
+      node_flux<NV, DIR>(a.pp, Uc, Fc);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sW[(NV + v) * TMW + q] = Fc[v];
+    }
   }
   __syncthreads();
 
@@ -410,19 +422,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
     const double* u = sU + q;        // node t + k of column c at u[k W]
     double res[NV], Un[NV];
     if (a.diff == 0) {
-      double Um[NV], Up[NV], Fm[NV], Fp[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        Um[v] = u[v * SV + 3 * W];
         Un[v] = u[v * SV + 4 * W];
-        Up[v] = u[v * SV + 5 * W];
-      }
-      node_flux<NV, DIR>(a.pp, Um, Fm);
-      node_flux<NV, DIR>(a.pp, Up, Fp);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
         const double* fv = f + v * TMW;
-        const double d = 1.5 * (fv[2 * W] - fv[W]) - 0.3 * (Fp[v] - Fm[v]) +
+        // F of node t + k + 2 at nf[k W]: nodes t + 3 and t + 5 around t + 4
+        const double* nf = f + (NV + v) * TMW;
+        const double d = 1.5 * (fv[2 * W] - fv[W]) - 0.3 * (nf[3 * W] - nf[W]) +
                          (1.0 / 30.0) * (fv[3 * W] - fv[0]);
         res[v] = -ih * d;
       }
