@@ -26,7 +26,9 @@
  *  - Host-side validation failures return WCNS_EINVAL before anything is
  *    enqueued; wcns_last_error() then describes the problem.  Device-side
  *    problems (a non-finite value, rho <= 0 or p <= 0 after a stage) are
- *    OR-ed into *status_dev (bit 0) and surface when the caller reads it.
+ *    OR-ed into *status_dev (bit 0) and surface when the caller reads it;
+ *    bit 1 reports a capped batch launch shorter than its live-tile list
+ *    (wcns_batch_rk3_steps_capped).
  *  - No exception or abort crosses this interface.  A plan must not be used
  *    by two host threads at once, and two calls that share a workspace must
  *    not overlap on the device.
