@@ -169,6 +169,41 @@ void interp_params(const wcns_desc* d, InterpParams* ip) {
     }
   }
   ip->Ke = ip->shared_exp ? std::exp(2.0 * d->xi - ip->C2[0] - ip->C2[1] - ip->C2[2]) : 0.0;
+  // Polynomial coefficients of the maps in E (fe_map_poly), in long double
+  // from the K_j: elementary symmetric polynomials e_r of the map's K_j for
+  // the denominator prod_j (1 + E K_j), and of the K_l, l != j, weighted by
+  // -2 a_j and -2 b_j for the numerator.
+  const double* fa[3] = {ip->weno ? kV0a : kG0a, ip->weno ? kV1a : kG1a, ip->weno ? kV2a : kG2a};
+  const double* fb[3] = {ip->weno ? kV0b : kG0b, ip->weno ? kV1b : kG1b, ip->weno ? kV2b : kG2b};
+  const int offd[3] = {0, 3, 7}, offp[3] = {0, 2, 5};
+  auto esym = [](const long double* x, int n, long double* e) {  // e[0..n]
+    e[0] = 1.0L;
+    for (int r = 1; r <= n; ++r) e[r] = 0.0L;
+    for (int i = 0; i < n; ++i)
+      for (int r = i + 1; r >= 1; --r) e[r] += x[i] * e[r - 1];
+  };
+  for (int m = 0; m < 3; ++m) {
+    const int nt = count[m];
+    long double K[4], e[5], ex[5], pa[4] = {0, 0, 0, 0}, pb[4] = {0, 0, 0, 0};
+    for (int j = 0; j < nt; ++j) K[j] = ip->shared_exp ? (long double)ip->K[first[m] + j] : 0.0L;
+    esym(K, nt, e);
+    for (int r = 1; r <= nt; ++r) ip->Pd[offd[m] + r - 1] = (double)e[r];
+    for (int j = 0; j < nt; ++j) {
+      long double rest[3];
+      int n = 0;
+      for (int l = 0; l < nt; ++l)
+        if (l != j) rest[n++] = K[l];
+      esym(rest, n, ex);
+      for (int r = 1; r < nt; ++r) {
+        pa[r] += -2.0L * fa[m][j] * ex[r];
+        pb[r] += -2.0L * fb[m][j] * ex[r];
+      }
+    }
+    for (int r = 1; r < nt; ++r) {
+      ip->Pa[offp[m] + r - 1] = (double)pa[r];
+      ip->Pb[offp[m] + r - 1] = (double)pb[r];
+    }
+  }
 }
 
 int device_cus() {

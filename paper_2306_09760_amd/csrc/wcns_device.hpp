@@ -54,13 +54,19 @@ struct InterpParams {
   //   shared_exp = 0:  K[j] = nu_j                      (C2 unused)
   double K[10];
   double C2[3];
-  double Ke;        // exp(2 xi - C2[0] - C2[1] - C2[2]) (shared_exp; fe_map_frac)
+  double Ke;        // exp(2 xi - C2[0] - C2[1] - C2[2]) (shared_exp; weigh5)
+  // fe_map_poly (shared_exp): per map m with NT_m terms, the coefficients
+  // of E^r in prod_j D_j (r = 1..NT_m; the constant is 1) and in the two
+  // parts of sum_j -2 A_j(w) prod_{l != j} D_l, alpha (constant in w) and
+  // beta (times w) (r = 1..NT_m - 1; the constants vanish), D_j = 1 + E K_j;
+  // maps at offsets 0, 3, 7 of Pd and 0, 2, 5 of Pa and Pb
+  double Pd[10], Pa[7], Pb[7];
   int weights;      // WJS .. WLIN
   int zpow;         // exponent p of eq. 14 (1..4)
   int shared_exp;   // 1: one exponential per map (xi * max|nu - c| < 300)
   int weno;         // 1: K, C2 hold the Table B.2 maps (WENO family)
   int fast_fe;      // 1: shared_exp and the unclamped products of the
-                    //    SPEC_FE path stay below e^600 (see fe_map_frac)
+                    //    SPEC_FE path stay below e^600 (see fe_map_poly)
 };
 
 // Physics parameters of one sweep.
@@ -276,33 +282,29 @@ __device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double*
 // (469 at xi = 100, kappa = 0.5).  The host selects this path only while
 // B < 600 (fast_fe), which leaves e^100 of headroom for the candidate values
 // that multiply the products; below e^-45 a q_j rounds away against 1.
-// E = exp(2 xi w - C2) is the caller's (weigh5).
+// E = exp(2 xi w - C2) is the caller's (weigh5).  The numerator and the
+// denominator are polynomials in E whose coefficients are constants of the
+// plan (InterpParams::Pd, Pa, Pb): Horner's rule in E takes 8 (NT = 3) or
+// 11 (NT = 4) operations instead of 12 and 16 for the products of the D_j.
+// The denominator's coefficients are positive, so it has no cancellation;
+// with the plan's maps the polynomial form rounds g(w) within 3.4e-16 of
+// its exact value over w in [0, 1], as the product form does within 1.4e-16.
 template <int NT>
-__device__ __forceinline__ double fe_map_frac(double w, double E, const double (&a)[NT],
-                                              const double (&b)[NT], const double* K,
-                                              double* den) {
+__device__ __forceinline__ double fe_map_poly(double w, double E, const double* pd,
+                                              const double* pa, const double* pb, double* den) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
-  double D[NT], A[NT];  // A holds -2 A_j
+  double t = pd[NT - 1];
 #pragma unroll
-  for (int j = 0; j < NT; ++j) {
-    D[j] = __builtin_fma(E, K[j], 1.0);
-    // (constant where b_j = 0: an fma with a zero factor would not fold)
-    A[j] = b[j] == 0.0 ? -2.0 * a[j] : __builtin_fma(-2.0 * b[j], w, -2.0 * a[j]);
-  }
-  double num;
-  const double d01 = D[0] * D[1];
-  const double n01 = __builtin_fma(A[0], D[1], A[1] * D[0]);
-  if constexpr (NT == 3) {
-    num = __builtin_fma(n01, D[2], A[2] * d01);
-    *den = d01 * D[2];
-  } else {
-    const double d23 = D[2] * D[3];
-    const double n23 = __builtin_fma(A[2], D[3], A[3] * D[2]);
-    num = __builtin_fma(n01, d23, n23 * d01);
-    *den = d01 * d23;
+  for (int r = NT - 2; r >= 0; --r) t = __builtin_fma(t, E, pd[r]);
+  *den = __builtin_fma(t, E, 1.0);
+  double ta = pa[NT - 2], tb = pb[NT - 2];
+#pragma unroll
+  for (int r = NT - 3; r >= 0; --r) {
+    ta = __builtin_fma(ta, E, pa[r]);
+    tb = __builtin_fma(tb, E, pb[r]);
   }
   // sum_j A_j(w) = 0 for every map (kMapSumsVanish), so g = w - 2 sum_j A_j / D_j.
-  return __builtin_fma(w, *den, num);
+  return __builtin_fma(w, *den, E * __builtin_fma(w, tb, ta));
 }
 
 // Constants of one scheme family in the FE fast path of weigh5: the ideal
@@ -356,11 +358,11 @@ __device__ __forceinline__ double weigh5(const InterpParams& P, double c0, doubl
     const double Ex1 = TAB ? exp_tab(zE1, xt) : exp_cw(zE1);
     const double Ex2 = P.Ke * rcp(Ex0 * Ex1);
     // g_k = n_k / e_k; the normalised weights g_k / sum_l g_l over the
-    // common denominator e_0 e_1 e_2 (below e^B, fe_map_frac): one reciprocal.
+    // common denominator e_0 e_1 e_2 (below e^B, fe_map_poly): one reciprocal.
     double e0, e1, e2;
-    const double n0 = fe_map_frac<3>(w0, Ex0, FAM::m0a, FAM::m0b, P.K, &e0);
-    const double n1 = fe_map_frac<4>(w1, Ex1, FAM::m1a, FAM::m1b, P.K + 3, &e1);
-    const double n2 = fe_map_frac<3>(w2, Ex2, FAM::m2a, FAM::m2b, P.K + 7, &e2);
+    const double n0 = fe_map_poly<3>(w0, Ex0, P.Pd, P.Pa, P.Pb, &e0);
+    const double n1 = fe_map_poly<4>(w1, Ex1, P.Pd + 3, P.Pa + 2, P.Pb + 2, &e1);
+    const double n2 = fe_map_poly<3>(w2, Ex2, P.Pd + 7, P.Pa + 5, P.Pb + 5, &e2);
     // T_k = n_k prod_{l != k} e_l: T_0 = A e_2, T_1 = B e_2, T_2 = C
     const double A = n0 * e1, B = n1 * e0, C = n2 * (e0 * e1);
     const double num = __builtin_fma(e2, __builtin_fma(A, c0, B * c1), C * c2);
