@@ -55,10 +55,13 @@ struct InterpParams {
   double K[10];
   double C2[3];
   double Ke;        // exp(2 xi - C2[0] - C2[1] - C2[2]) (shared_exp; weigh5)
-  // fe_map_poly (shared_exp): per map m with NT_m terms, the coefficients
-  // of E^r in prod_j D_j (r = 1..NT_m; the constant is 1) and in the two
-  // parts of sum_j -2 A_j(w) prod_{l != j} D_l, alpha (constant in w) and
-  // beta (times w) (r = 1..NT_m - 1; the constants vanish), D_j = 1 + E K_j;
+  // fe_map_poly (shared_exp): per map m with NT_m terms, prod_j D_j and the
+  // two parts of sum_j -2 A_j(w) prod_{l != j} D_l, alpha (constant in w)
+  // and beta (times w), D_j = 1 + E K_j, as polynomials in E divided by the
+  // leading coefficient prod_j K_j (= 1 up to rounding: c_m is the mean of
+  // the map's null points), so that the denominator is monic:
+  //   Pd = [c_1 .. c_{NT-1}, c_0] for E^NT + c_{NT-1} E^{NT-1} + .. + c_0,
+  //   Pa, Pb = the coefficients of E^1 .. E^{NT-1} (the constants vanish);
   // maps at offsets 0, 3, 7 of Pd and 0, 2, 5 of Pa and Pb
   double Pd[10], Pa[7], Pb[7];
   int weights;      // WJS .. WLIN
@@ -289,14 +292,17 @@ __device__ __forceinline__ double fe_g2(double w, const InterpParams& P, double*
 // The denominator's coefficients are positive, so it has no cancellation;
 // with the plan's maps the polynomial form rounds g(w) within 3.4e-16 of
 // its exact value over w in [0, 1], as the product form does within 1.4e-16.
+// The denominator is monic, so its Horner chain starts from E + c_{NT-1}
+// (no instruction with two constant operands, which the vector ALU cannot
+// read in one operation).
 template <int NT>
 __device__ __forceinline__ double fe_map_poly(double w, double E, const double* pd,
                                               const double* pa, const double* pb, double* den) {
   static_assert(NT == 3 || NT == 4, "maps have three or four terms");
-  double t = pd[NT - 1];
+  double t = E + pd[NT - 2];
 #pragma unroll
-  for (int r = NT - 2; r >= 0; --r) t = __builtin_fma(t, E, pd[r]);
-  *den = __builtin_fma(t, E, 1.0);
+  for (int r = NT - 3; r >= 0; --r) t = __builtin_fma(t, E, pd[r]);
+  *den = __builtin_fma(t, E, pd[NT - 1]);
   double ta = pa[NT - 2], tb = pb[NT - 2];
 #pragma unroll
   for (int r = NT - 3; r >= 0; --r) {
