@@ -230,11 +230,7 @@ wcns_status wcns_plan_set_tiles(wcns_plan* plan, const int32_t tiles[3]);
    offsets_host[p] .. offsets_host[p+1]-1 of every variable of the batch
    state U[v*total + column], total = offsets_host[nprob]; its spacing is
    h_host[p].  The library copies offsets and h to small device tables of
-   its own, and builds a table of the state index of every slot of every
-   tile (4 bytes per slot, about 4 bytes per node; rebuilt when the tile
-   size changes), synchronously; all are freed by wcns_batch_plan_destroy.
-   WCNS_EUNSUPPORTED for total >= 2^31 (the slot table holds 31-bit
-   indices). */
+   its own (synchronously; freed by wcns_batch_plan_destroy). */
 wcns_status wcns_batch_plan_create(const wcns_desc* proto, int64_t nprob,
                                    const int64_t* offsets_host, const double* h_host,
                                    wcns_batch_plan** plan);

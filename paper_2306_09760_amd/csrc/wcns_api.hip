@@ -250,7 +250,6 @@ struct wcns_batch_plan {
   double* d_ih = nullptr;
   int32_t* d_tile_p0 = nullptr;
   int32_t* d_tile_p1 = nullptr;
-  int32_t* d_slot = nullptr;  // per-tile slot table (BatchArgs::slot), or null
   int32_t ntiles = 0;
   int tm = 128;
   int grid = 0;
@@ -888,41 +887,6 @@ static wcns_status batch_build_tiles(wcns_batch_plan* B) {
   WCNS_HIP(hipMalloc(&B->d_tile_p1, sizeof(int32_t) * tq.size()), "hipMalloc tiles");
   WCNS_HIP(hipMemcpy(B->d_tile_p0, tp.data(), sizeof(int32_t) * tp.size(), hipMemcpyHostToDevice), "copy tiles");
   WCNS_HIP(hipMemcpy(B->d_tile_p1, tq.data(), sizeof(int32_t) * tq.size(), hipMemcpyHostToDevice), "copy tiles");
-  // The slot table: for each tile's TM + 5 load slots v = k TL - G + r, the
-  // problem p whose slot range holds v (the first or the last one for slots
-  // before or after every range), its node j = v - start(p) - G clamped to
-  // [-G, N_p + G) and mapped onto a node by the boundary condition, as the
-  // kernel's own slot arithmetic does; bit 31 marks a ghost slot.
-  if (B->d_slot) hipFree(B->d_slot);
-  B->d_slot = nullptr;
-  const int TN = B->tm + 5;
-  if (B->total >= (int64_t(1) << 31) || nt * (int64_t)TN >= (int64_t(1) << 31))
-    return fail(WCNS_EUNSUPPORTED, "batch of %lld nodes: the slot table takes 31-bit indices",
-                (long long)B->total);
-  {
-    std::vector<int32_t> slot((size_t)(nt * TN));
-    int64_t ps = 0;
-    for (int64_t k = 0; k < nt; ++k) {
-      for (int r = 0; r < TN; ++r) {
-        const int64_t v = k * TL - G + r;
-        while (ps + 1 < np && start(ps + 1) <= v) ++ps;
-        int64_t p = ps;
-        while (p > 0 && start(p) > v) --p;
-        const int n = (int)(B->h_offset[p + 1] - B->h_offset[p]);
-        int64_t j = v - start(p) - G;
-        j = j < -G ? -G : (j >= n + G ? n + G - 1 : j);
-        const bool ghost = j < 0 || j >= n;
-        int64_t jj = j;
-        if (B->d.bc[0] == WCNS_BC_PERIODIC) jj = j < 0 ? j + n : (j >= n ? j - n : j);
-        else jj = j < 0 ? 0 : (j >= n ? n - 1 : j);
-        const int64_t gi = B->h_offset[p] + jj;
-        slot[(size_t)(k * TN + r)] = (int32_t)((uint32_t)gi | (ghost ? 0x80000000u : 0u));
-      }
-    }
-    WCNS_HIP(hipMalloc(&B->d_slot, sizeof(int32_t) * slot.size()), "hipMalloc slot table");
-    WCNS_HIP(hipMemcpy(B->d_slot, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice),
-             "copy slot table");
-  }
   // one workgroup per tile
   B->grid = B->ntiles;
   if (B->exec) {
@@ -1001,7 +965,6 @@ wcns_status wcns_batch_plan_destroy(wcns_batch_plan* B) {
   if (B->d_ih) hipFree(B->d_ih);
   if (B->d_tile_p0) hipFree(B->d_tile_p0);
   if (B->d_tile_p1) hipFree(B->d_tile_p1);
-  if (B->d_slot) hipFree(B->d_slot);
   delete B;
   return WCNS_OK;
 }
@@ -1030,7 +993,6 @@ static void batch_args(const wcns_batch_plan* B, double* dtp, SweepArgs* a, Batc
   b->tile_p1 = B->d_tile_p1;
   b->ntiles = B->ntiles;
   b->nprob = (int32_t)B->nprob;
-  b->slot = B->d_slot;
   // stage launches walk the live-tile list in the workspace
   b->live = work ? (const int32_t*)((const char*)work + B->off_live) : nullptr;
   b->nlive = work ? (const int32_t*)((const char*)work + B->off_nlive) : nullptr;

@@ -57,10 +57,6 @@ struct BatchArgs {
   const int32_t* tile_p1;  //   loads (outputs and halo) touch
   const int32_t* live;     // live tiles in increasing order by runs (null: all tiles)
   const int32_t* nlive;    // length of the live list (device)
-  // per tile, the state index of each of its TM + 5 load slots (ghosts
-  // applied), bit 31 set where the slot is a ghost (no node of a problem):
-  // slot[tile (TM + 5) + r] for slot i0 - G + r
-  const int32_t* slot;
   int32_t ntiles;
   int32_t nprob;
 };

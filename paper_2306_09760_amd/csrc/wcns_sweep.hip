@@ -166,10 +166,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
   constexpr int NIT = (SV + NT - 1) / NT;
   static_assert(NIT <= 2, "a tile holds at most two nodes per lane");
   double buf[NIT][NV];
-  // the batch plan's per-tile slot table: one load per slot instead of the
-  // slot-to-problem arithmetic
-  const int32_t* tab = nullptr;
-  if constexpr (BATCH) tab = b.slot + tile * (int64_t)SV;
 #pragma unroll
   for (int it = 0; it < NIT; ++it) {
     const int idx = tid + it * NT;
@@ -177,11 +173,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
       const int k = idx >> LW, c = idx & (W - 1);
       const int cc = c < ncol ? c : ncol - 1;
       int64_t gi;
-      if constexpr (BATCH) {
-        gi = tab[idx] & 0x7fffffff;
-      } else if constexpr (LINES) {
-        const BatchSlot sl =
-            near ? batch_slot_near(bt, k - G) : line_slot(nb + k, N, g.lines, G, g.inv_line);
+      if constexpr (LINES) {
+        BatchSlot sl;
+        if (near)
+          sl = batch_slot_near(bt, k - G);
+        else if constexpr (BATCH)
+          sl = batch_slot(b, bt.p0, bt.p1, G, nb + k);
+        else
+          sl = line_slot(nb + k, N, g.lines, G, g.inv_line);
         // slots outside every problem's range (before the first, after the
         // last) load a ghost; no output node uses them
         const int j = sl.j < -G ? -G : (sl.j >= sl.n + G ? sl.n + G - 1 : sl.j);
@@ -200,19 +199,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
   if constexpr (LINES) {
     static_assert(W == 1 && TM <= NT, "one output node per lane");
     if (tid < TL) {
-      if constexpr (BATCH) {
-        const int32_t e = tab[tid + G];  // slot i0 + tid
-        if (e >= 0) {
-          onode = e;
-          oprob = near ? bt.p0 + (tid >= bt.r1 ? 1 : 0) : batch_slot(b, bt.p0, bt.p1, G, i0 + tid).p;
-        }
-      } else {
-        const BatchSlot sl =
-            near ? batch_slot_near(bt, tid) : line_slot(i0 + tid, N, g.lines, G, g.inv_line);
-        if (sl.j >= 0 && sl.j < sl.n) {
-          onode = sl.o + sl.j;
-          oprob = sl.p;
-        }
+      BatchSlot sl;
+      if (near)
+        sl = batch_slot_near(bt, tid);
+      else if constexpr (BATCH)
+        sl = batch_slot(b, bt.p0, bt.p1, G, i0 + tid);
+      else
+        sl = line_slot(i0 + tid, N, g.lines, G, g.inv_line);
+      if (sl.j >= 0 && sl.j < sl.n) {
+        onode = sl.o + sl.j;
+        oprob = sl.p;
       }
     }
   }
