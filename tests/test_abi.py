@@ -135,6 +135,31 @@ def test_batch_plan_validation_on_host(L):
     assert st == L.WCNS_EINVAL
 
 
+@pytest.mark.parametrize("nprob,offsets,h,msg", [
+    (0, [0], [], "nprob"),                          # empty batch
+    (2, [1, 20, 40], [0.1, 0.1], "offsets[0]"),     # does not start at node 0
+    (2, [0, 30, 25], [0.1, 0.1], "nodes"),          # decreasing offsets
+    (2, [0, 9, 18], [0.1, 0.0], "h["),              # zero spacing
+    (2, [0, 9, 18], [0.1, -0.2], "h["),             # negative spacing
+    (2, [0, 9, 18], [float("nan"), 0.1], "h["),     # NaN spacing
+    (2, [0, 9, 18], [0.1, float("inf")], "h["),     # infinite spacing
+])
+def test_degenerate_batches_rejected_on_host(L, nprob, offsets, h, msg):
+    """Batch plans that describe no valid set of problems fail with
+    WCNS_EINVAL before any device memory is touched."""
+    import numpy as np
+    lib = L.lib()
+    d = L.make_desc(system="euler", ndim=1, n=(9,), bc="transmissive")
+    off = np.array(offsets, dtype=np.int64)
+    hh = np.array(h if h else [1.0], dtype=np.float64)
+    out = C.c_void_p()
+    st = lib.wcns_batch_plan_create(C.byref(d), nprob, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                    hh.ctypes.data_as(C.POINTER(C.c_double)), C.byref(out))
+    assert st == L.WCNS_EINVAL
+    assert msg in lib.wcns_last_error().decode()
+    assert not out.value
+
+
 def test_product_path_has_no_cpu_fallback():
     """The package never imports the oracle and refuses to run without a
     device."""
