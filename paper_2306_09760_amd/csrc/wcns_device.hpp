@@ -776,14 +776,32 @@ __device__ __forceinline__ double wave_rate(const double* U, double gamma, const
 // Maxima of wave rates are taken on their bit patterns as unsigned integers:
 // for non-negative doubles that is the order of the values, and a NaN (of
 // either sign) exceeds every finite rate, so it always reaches dt.  Maximum
-// over the 64 lanes of a wavefront (all lanes active).
+// over the 64 lanes of a wavefront (all lanes active), by DPP lane moves
+// (vector-ALU operations, where each step of a lane-permute exchange would
+// be a round trip through the LDS crossbar): the maximum within quads, rows
+// of 16 by two right shifts, then rows 0 -> 1, 2 -> 3 and the first half ->
+// the second by row broadcasts, which leaves the wavefront's maximum in
+// lane 63.  Lanes that a move leaves out read 0, the neutral value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, ROWS, 0xf, true);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL, ROWS, 0xf, true);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) {
+  return b > a ? b : a;
+}
 __device__ __forceinline__ unsigned long long wave_max_bits(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long w = __shfl_xor(v, o, 64);
-    v = w > v ? w : v;
-  }
-  return v;
+  v = umax64(v, dpp_u64<0xb1, 0xf>(v));   // quad_perm [1, 0, 3, 2]
+  v = umax64(v, dpp_u64<0x4e, 0xf>(v));   // quad_perm [2, 3, 0, 1]
+  v = umax64(v, dpp_u64<0x114, 0xf>(v));  // row_shr:4
+  v = umax64(v, dpp_u64<0x118, 0xf>(v));  // row_shr:8
+  v = umax64(v, dpp_u64<0x142, 0xa>(v));  // row_bcast:15 into rows 1 and 3
+  v = umax64(v, dpp_u64<0x143, 0xc>(v));  // row_bcast:31 into rows 2 and 3
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
 }
 
 // Wave speed |u_DIR| + c of one state along DIR.
