@@ -329,6 +329,23 @@ wcns_status wcns_probe_fp64_fma(double* out, int32_t blocks, int32_t iters, void
    (device arrays, 16-byte aligned, not overlapping; WCNS_EINVAL otherwise).
    The caller times it: 16 n bytes move. */
 wcns_status wcns_probe_copy(const double* src, double* dst, int64_t n, void* stream);
+/* The device's elementary functions, out[i] = f(x[i]) for i < n (device
+   arrays of doubles, owned by the caller), so that their error bounds can be
+   checked against a reference: e^z through the 2^(k/64) table (Tang's
+   method, |z| <= 708), e^z by Cody-Waite reduction and a degree-13 Taylor
+   polynomial (|z| <= 708), 1/x with two and with one Newton step from the
+   hardware seed (x normal), and the square root of 0 or of x in
+   [2^-760, inf).  These are the exponentials, reciprocals and square roots
+   of the residual (Sec. 2, eq. 20; the Roe average and the fluxes).
+   WCNS_EINVAL for a NULL pointer, n < 0 or an unknown fn. */
+typedef enum {
+  WCNS_MATH_EXP_TAB = 0,
+  WCNS_MATH_EXP_CW = 1,
+  WCNS_MATH_RCP = 2,
+  WCNS_MATH_RCP1 = 3,
+  WCNS_MATH_SQRT = 4
+} wcns_math_fn;
+wcns_status wcns_probe_math(const double* x, double* out, int64_t n, int32_t fn, void* stream);
 
 const char* wcns_status_string(wcns_status s);
 /* Message of the last failing call on this host thread ("" if none). */

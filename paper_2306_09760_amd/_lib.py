@@ -36,7 +36,7 @@ EXPORTS = [
     "wcns_batch_residual", "wcns_batch_rk3_step", "wcns_batch_rk3_steps", "wcns_batch_set_graph", "wcns_batch_last_dt",
     "wcns_batch_live_tiles", "wcns_batch_rk3_steps_capped",
     "wcns_batch_autotune", "wcns_batch_get_tile", "wcns_batch_set_tile",
-    "wcns_batch_cfl", "wcns_batch_stage", "wcns_probe_fp64_fma", "wcns_probe_copy",
+    "wcns_batch_cfl", "wcns_batch_stage", "wcns_probe_fp64_fma", "wcns_probe_copy", "wcns_probe_math",
     "wcns_status_string", "wcns_last_error",
 ]
 
@@ -109,6 +109,7 @@ def lib():
         "wcns_batch_set_tile": (st, [vp, C.c_int32]),
         "wcns_probe_fp64_fma": (st, [vp, C.c_int32, C.c_int32, vp]),
         "wcns_probe_copy": (st, [vp, vp, C.c_int64, vp]),
+        "wcns_probe_math": (st, [vp, vp, C.c_int64, C.c_int32, vp]),
         "wcns_status_string": (C.c_char_p, [st]),
         "wcns_last_error": (C.c_char_p, []),
     }

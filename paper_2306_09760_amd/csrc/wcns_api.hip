@@ -1287,6 +1287,15 @@ wcns_status wcns_probe_copy(const double* src, double* dst, int64_t n, void* str
   return WCNS_OK;
 }
 
+wcns_status wcns_probe_math(const double* x, double* out, int64_t n, int32_t fn, void* stream) {
+  g_err.clear();
+  if (!x || !out) return fail(WCNS_EINVAL, "NULL argument");
+  if (n < 0) return fail(WCNS_EINVAL, "n must be >= 0");
+  if (fn < WCNS_MATH_EXP_TAB || fn > WCNS_MATH_SQRT) return fail(WCNS_EINVAL, "unknown function %d", fn);
+  WCNS_HIP(launch_probe_math(x, out, n, fn, (hipStream_t)stream), "probe launch");
+  return WCNS_OK;
+}
+
 const char* wcns_status_string(wcns_status s) {
   switch (s) {
     case WCNS_OK: return "ok";

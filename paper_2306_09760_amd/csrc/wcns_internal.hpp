@@ -140,5 +140,6 @@ int cfl_blocks(int64_t npts);
 
 hipError_t launch_probe_fma(double* out, int blocks, int iters, hipStream_t stream);
 hipError_t launch_probe_copy(const double* src, double* dst, int64_t n, hipStream_t stream);
+hipError_t launch_probe_math(const double* x, double* out, int64_t n, int fn, hipStream_t stream);
 
 }  // namespace wcns

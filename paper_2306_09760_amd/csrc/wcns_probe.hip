@@ -1,7 +1,8 @@
 // Roof probes of gfx950 (measurement only, not part of the method): a
 // register-resident FP64 FMA stream for the vector-ALU roof and a 16-byte
 // streaming copy for the HBM roof.  Both sizes come from the caller, which
-// times them.
+// times them.  And the device's elementary functions (exp_tab, exp_cw, rcp,
+// rcp1, sqrt_pos) applied to an array, for checks of their error bounds.
 #include <hip/hip_runtime.h>
 
 #include "wcns_internal.hpp"
@@ -49,6 +50,39 @@ __global__ void __launch_bounds__(256) probe_copy_kernel(const double2* __restri
 __global__ void probe_copy_tail_kernel(const double* __restrict__ src, double* __restrict__ dst,
                                        int64_t i) {
   dst[i] = src[i];
+}
+
+// out[i] = f(x[i]) for the elementary function f selected by fn (0 exp_tab,
+// 1 exp_cw, 2 rcp, 3 rcp1, 4 sqrt_pos), grid-stride; exp_tab reads the
+// 2^(k/64) table from LDS as the sweep kernels do.
+__global__ void __launch_bounds__(256) probe_math_kernel(const double* __restrict__ x,
+                                                         double* __restrict__ out, int64_t n,
+                                                         int fn) {
+  __shared__ double sX[64];
+  if (threadIdx.x < 64) sX[threadIdx.x] = kExp2Tab64[threadIdx.x];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = x[i];
+    double y;
+    switch (fn) {
+      case 0: y = exp_tab(v, sX); break;
+      case 1: y = exp_cw(v); break;
+      case 2: y = rcp(v); break;
+      case 3: y = rcp1(v); break;
+      default: y = sqrt_pos(v); break;
+    }
+    out[i] = y;
+  }
+}
+
+hipError_t launch_probe_math(const double* x, double* out, int64_t n, int fn, hipStream_t stream) {
+  if (n > 0) {
+    const int64_t want = (n + 255) / 256;
+    const int blocks = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(probe_math_kernel, dim3(blocks), dim3(256), 0, stream, x, out, n, fn);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_probe_fma(double* out, int blocks, int iters, hipStream_t stream) {

@@ -160,6 +160,18 @@ def test_degenerate_batches_rejected_on_host(L, nprob, offsets, h, msg):
     assert not out.value
 
 
+def test_math_probe_validates_on_host(L):
+    """wcns_probe_math rejects an unknown function, a NULL array or n < 0
+    before any device work."""
+    lib = L.lib()
+    buf = (C.c_double * 4)()
+    p = C.cast(buf, C.c_void_p)
+    assert lib.wcns_probe_math(p, p, 4, 5, None) == L.WCNS_EINVAL
+    assert lib.wcns_probe_math(p, p, 4, -1, None) == L.WCNS_EINVAL
+    assert lib.wcns_probe_math(None, p, 4, 0, None) == L.WCNS_EINVAL
+    assert lib.wcns_probe_math(p, p, -1, 0, None) == L.WCNS_EINVAL
+
+
 def test_product_path_has_no_cpu_fallback():
     """The package never imports the oracle and refuses to run without a
     device."""
