@@ -399,7 +399,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
   __syncthreads();
 
   // flux difference and output
-  const EmitArgs ea = emit_args(sweep_kernargs_late()->a);
+  EmitArgs ea = emit_args(sweep_kernargs_late()->a);
+  // a batch stage has no residual of earlier sweeps (one direction):
+  // known here, its reads and selects drop out of the epilogue
+  if constexpr (BATCH) ea.Rin = nullptr;
   unsigned long long rbits = 0;  // wave rate of the lane's written node (SweepArgs::wmax)
 #pragma unroll 1
   for (int q = tid; q < TL * W; q += NT) {
