@@ -50,7 +50,9 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
   const double zE0 = __builtin_fma(xi2, z[0], -P.C2[0]), zE1 = __builtin_fma(xi2, z[1], -P.C2[1]);
   const double E0 = TAB ? exp_tab(zE0, xt) : exp_cw(zE0);
   const double E1 = TAB ? exp_tab(zE1, xt) : exp_cw(zE1);
-  const double E2 = P.Ke * rcp(E0 * E1);
+  // the reciprocals below that do not feed an exponential's argument take
+  // one Newton step (rcp1), as in the forward fast path
+  const double E2 = P.Ke * rcp1(E0 * E1);
   double g[3], gp[3];
   auto map = [&](auto ntc, int k, const double* av, const double* bv, const double* K, double E) {
     constexpr int NT = decltype(ntc)::value;
@@ -73,7 +75,7 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
       o[3] = d01 * D[2];
       e = d01 * d23;
     }
-    const double r = rcp(e);
+    const double r = rcp1(e);
     double gk = w, dk = 1.0;
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
@@ -89,7 +91,7 @@ __device__ __forceinline__ void fe_weights_vjp(const InterpParams& P, double c0,
   map(std::integral_constant<int, 3>{}, 0, kG0a, kG0b, P.K, E0);
   map(std::integral_constant<int, 4>{}, 1, kG1a, kG1b, P.K + 3, E1);
   map(std::integral_constant<int, 3>{}, 2, kG2a, kG2b, P.K + 7, E2);
-  const double rg = rcp(g[0] + g[1] + g[2]);
+  const double rg = rcp1(g[0] + g[1] + g[2]);
   const double w0 = g[0] * rg, w1 = g[1] * rg, w2 = g[2] * rg;
   c0b = w0 * yb;
   c1b = w1 * yb;
