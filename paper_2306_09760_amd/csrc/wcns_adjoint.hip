@@ -446,19 +446,19 @@ __global__ void __launch_bounds__(256)
         for (int gg = 1; gg <= G; ++gg) add_position(k + gg);
     }
     if (a.diff == 0) {
-      // node flux F_i enters D_{i+1} with -3/10 and D_{i-1} with +3/10
-      const int64_t lb = base + c;
+      // node flux F_i enters D_{i+1} with -3/10 and D_{i-1} with +3/10;
+      // Rbar of nodes i - 1 .. i + 1 from the tile's copy (sRB: the line's
+      // ghosts applied, zero beyond a transmissive end)
       double Fb[NV], U[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double* Rb = a.Rbar + v * a.npts;
-        double f = -0.3 * a.ih *
-                   (rbar_at(Rb, lb, stride, i + 1, N, a.bc) - rbar_at(Rb, lb, stride, i - 1, N, a.bc));
+        const double* Rb = sRB + v * SV + k * W + c;  // Rbar of node i
+        double f = -0.3 * a.ih * (Rb[W] - Rb[-W]);
         if (a.bc != 0) {
           if (i == 0)  // ghost node -1 carries U_0
-            f += -0.3 * a.ih * rbar_at(Rb, lb, stride, 0, N, a.bc);
+            f += -0.3 * a.ih * Rb[0];
           if (i == N - 1)  // ghost node N carries U_{N-1}
-            f += 0.3 * a.ih * rbar_at(Rb, lb, stride, N - 1, N, a.bc);
+            f += 0.3 * a.ih * Rb[0];
         }
         Fb[v] = f;
         U[v] = sU[v * SV + k * W + c];
