@@ -64,14 +64,6 @@ struct AdjLayout {
   static constexpr int waves = per_cu < 1 ? 1 : (per_cu > 4 ? 4 : per_cu);
 };
 
-// Rbar at position j of a line (zero outside a transmissive line).
-__device__ __forceinline__ double rbar_at(const double* Rb, int64_t base, int64_t stride,
-                                          int64_t j, int64_t N, int bc) {
-  if (bc == 0) return Rb[base + bc_index(j, N, 0) * stride];
-  if (j < 0 || j >= N) return 0.0;
-  return Rb[base + j * stride];
-}
-
 // Register budget for the waves per SIMD that the tile's LDS allows.
 template <int NV, int DIR, int SPEC, int TM, int W>
 __global__ void __launch_bounds__(256)
@@ -158,12 +150,15 @@ __global__ void __launch_bounds__(256)
         for (int v = 0; v < NV; ++v)  // Rbar: zero at a transmissive ghost
           rbuf[it][v] = (ghost && a.bc != 0) ? 0.0 : a.Rbar[v * a.npts + gi];
       } else {
-        const int64_t gi = base + bc_index(nb + k, N, a.bc) * stride + cc;
+        // one index for both arrays: Rbar is zero where a transmissive
+        // line's ghost copies its end node
+        const int64_t j = nb + k;
+        const int64_t gi = base + bc_index(j, N, a.bc) * stride + cc;
+        const bool ghost = a.bc != 0 && (j < 0 || j >= N);
 #pragma unroll
         for (int v = 0; v < NV; ++v) buf[it][v] = a.U[v * a.npts + gi];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-          rbuf[it][v] = rbar_at(a.Rbar + v * a.npts, base + cc, stride, nb + k, N, a.bc);
+        for (int v = 0; v < NV; ++v) rbuf[it][v] = ghost ? 0.0 : a.Rbar[v * a.npts + gi];
       }
     }
   }
