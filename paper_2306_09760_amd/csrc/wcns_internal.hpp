@@ -63,6 +63,26 @@ struct BatchArgs {
 
 // Geometry of a sweep's tiles: tm midpoints along the sweep direction by w
 // adjacent x-columns (w = 1 along x); tm*w is 128 or 256 (powers of two).
+// Division of a tile index n < 2^31 by a divisor 1 <= d < 2^31 fixed for a
+// launch, by a multiply and a shift (Granlund and Montgomery, PLDI 1994):
+// with l = ceil(log2 d) and m = ceil(2^(31+l) / d) < 2^32, m d = 2^(31+l) + e
+// with 0 <= e < d <= 2^l, so n m / 2^(31+l) exceeds n/d by less than 1/d
+// and its floor is floor(n/d).  On the device this is a few scalar
+// instructions where a 64-bit division is a long branchy sequence.
+struct FastDiv {
+  uint32_t m;
+  int32_t sh;  // 31 + l
+  __host__ __device__ uint32_t div(uint32_t n) const {
+    return (uint32_t)(((uint64_t)n * m) >> sh);
+  }
+};
+inline FastDiv fast_div(uint32_t d) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t num = 1ull << (31 + l);
+  return FastDiv{(uint32_t)((num + d - 1) / d), 31 + l};
+}
+
 struct TileGeom {
   int tm, w, lw, ltmw;   // lw = log2 w, ltmw = log2 (tm w)
   int tl;                // nodes per tile and column: tm - 3 (MND6) or tm - 5 (MD6)
@@ -74,6 +94,7 @@ struct TileGeom {
   int64_t lines;
   double inv_line;       // 1 / L
   int64_t grid;          // workgroups launched (0: ntiles)
+  FastDiv dxg, dseg;     // division by xgroups and by segs (y and z sweeps)
 };
 
 // Launchers.  All enqueue on `stream` and return the hipError_t of the launch

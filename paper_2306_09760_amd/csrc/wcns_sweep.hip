@@ -140,10 +140,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
     if (mode >= MODE_STAGE) dt = *a.dt;
   } else {
     // column groups fastest: adjacent groups split the same cache lines
-    const int64_t xg = tile % g.xgroups;
-    const int64_t r = tile / g.xgroups;
-    const int64_t seg = r % g.segs;
-    const int64_t other = r / g.segs;
+    // tile < 2^31 (checked at launch): multiply-shift divisions
+    const uint32_t t32 = (uint32_t)tile;
+    const uint32_t r32 = g.dxg.div(t32);
+    const uint32_t o32 = g.dseg.div(r32);
+    const int64_t xg = t32 - r32 * (uint32_t)g.xgroups;
+    const int64_t seg = r32 - o32 * (uint32_t)g.segs;
+    const int64_t other = o32;
     i0 = seg * TL;
     const int64_t x0 = xg * W;
     ncol = (int)((a.n[0] - x0) < W ? (a.n[0] - x0) : W);
@@ -588,6 +591,9 @@ static TileGeom make_geom(int dir, const int64_t n[3], int diff, int tm, int w) 
   g.tl = tm - (diff ? 5 : 3);
   g.segs = ceil_div64(n[dir], g.tl);
   g.xgroups = dir == 0 ? 1 : ceil_div64(n[0], w);
+  // (both below 2^31 whenever the tile count is, which the launch checks)
+  g.dxg = fast_div((uint32_t)g.xgroups);
+  g.dseg = fast_div((uint32_t)g.segs);
   const int64_t others = dir == 0 ? n[1] * n[2] : (dir == 1 ? n[2] : n[1]);
   g.ntiles = g.segs * g.xgroups * others;
   g.lines = 0;

@@ -57,10 +57,13 @@ __global__ void __launch_bounds__(256) weno_sweep_kernel(SweepArgs a, TileGeom g
   int64_t base, N, stride;
   int ncol = 1;
   // column groups fastest: adjacent groups split the same cache lines
-  const int64_t xg = tile % g.xgroups;
-  const int64_t r = tile / g.xgroups;
-  const int64_t seg = r % g.segs;
-  const int64_t other = r / g.segs;
+  // tile < 2^31 (checked at launch): multiply-shift divisions
+  const uint32_t t32 = (uint32_t)tile;
+  const uint32_t r32 = g.dxg.div(t32);
+  const uint32_t o32 = g.dseg.div(r32);
+  const int64_t xg = t32 - r32 * (uint32_t)g.xgroups;
+  const int64_t seg = r32 - o32 * (uint32_t)g.segs;
+  const int64_t other = o32;
   const int64_t i0 = seg * TL;
   if constexpr (DIR == 0) {
     N = a.n[0];
@@ -250,6 +253,9 @@ static hipError_t weno_go(const SweepArgs& a, int mode, hipStream_t s) {
   g.tl = TM - 1;
   g.segs = (a.n[DIR] + g.tl - 1) / g.tl;
   g.xgroups = DIR == 0 ? 1 : (a.n[0] + W - 1) / W;
+  // (both below 2^31 whenever the tile count is, which the launch checks)
+  g.dxg = fast_div((uint32_t)g.xgroups);
+  g.dseg = fast_div((uint32_t)g.segs);
   const int64_t others = DIR == 0 ? a.n[1] * a.n[2] : (DIR == 1 ? a.n[2] : a.n[1]);
   g.ntiles = g.segs * g.xgroups * others;
   if (g.ntiles > 0x7fffffff) return hipErrorInvalidConfiguration;
