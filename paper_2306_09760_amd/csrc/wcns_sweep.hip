@@ -318,13 +318,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
           roe_derived<ND>(rs, a.pp.gamma);
           double l[NV];
           field_row<ND, DIR>(rs, v, l);
-#pragma unroll
-          for (int j = 0; j < 6; ++j) {
-            double acc = l[0] * u[j * W];
-#pragma unroll
-            for (int e = 1; e < NV; ++e) acc = __builtin_fma(l[e], u[e * SV + j * W], acc);
-            w[j] = acc;
-          }
+          project_stencil<NV, SV, W>(u, l, w);
         }
       }
     } else {
