@@ -425,9 +425,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         Un[v] = u[v * SV + 4 * W];
-        const double* fv = f + v * TMW;
+        const lds_cptr fv = lds_row(f + v * TMW);
         // F of node t + k + 2 at nf[k W]: nodes t + 3 and t + 5 around t + 4
-        const double* nf = f + (NV + v) * TMW;
+        const lds_cptr nf = lds_row(f + (NV + v) * TMW);
         const double d = 1.5 * (fv[2 * W] - fv[W]) - 0.3 * (nf[3 * W] - nf[W]) +
                          (1.0 / 30.0) * (fv[3 * W] - fv[0]);
         res[v] = -ih * d;
@@ -436,7 +436,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs& a, const BatchArgs& 
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         Un[v] = u[v * SV + 5 * W];
-        const double* fv = f + v * TMW;
+        const lds_cptr fv = lds_row(f + v * TMW);
         const double d = (75.0 / 64.0) * (fv[3 * W] - fv[2 * W]) +
                          (-25.0 / 384.0) * (fv[4 * W] - fv[W]) + (3.0 / 640.0) * (fv[5 * W] - fv[0]);
         res[v] = -ih * d;

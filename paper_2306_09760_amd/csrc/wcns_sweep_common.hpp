@@ -137,21 +137,27 @@ __device__ __forceinline__ int bc_index_near(int j, int n, int bc) {
   return j < 0 ? 0 : (j >= n ? n - 1 : j);
 }
 
+// A row of a tile in LDS as its own address.  Paired LDS reads (two
+// doubles, offsets up to 2040 bytes from one address) of rows that lie
+// further apart than that would otherwise each get an address add; the
+// empty asm hides that the row is a constant offset of another address, so
+// all reads of the row share one.
+using lds_cptr = const __attribute__((address_space(3))) double*;
+__device__ __forceinline__ lds_cptr lds_row(const double* p) {
+  lds_cptr r = (lds_cptr)p;
+  asm volatile("" : "+v"(r));
+  return r;
+}
+
 // w_j = sum_e l_e u[e SV + j W], j = 0..5: one field of the six stencil
-// nodes from the tile's nodes in LDS (variable rows SV doubles apart).  One
-// LDS address per variable row: the empty asm hides that the rows are
-// constant offsets of one base, which the paired reads (offsets up to 2040
-// bytes) would otherwise reach through an address add per pair.
+// nodes from the tile's nodes in LDS (variable rows SV doubles apart), one
+// LDS address per variable row.
 template <int NV, int SV, int W>
 __device__ __forceinline__ void project_stencil(const double* u, const double (&l)[NV],
                                                 double (&w)[6]) {
-  using lds_cptr = const __attribute__((address_space(3))) double*;
   lds_cptr ur[NV];
 #pragma unroll
-  for (int e = 0; e < NV; ++e) {
-    ur[e] = (lds_cptr)(u + e * SV);
-    if (e > 0) asm volatile("" : "+v"(ur[e]));
-  }
+  for (int e = 0; e < NV; ++e) ur[e] = e > 0 ? lds_row(u + e * SV) : (lds_cptr)u;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     double acc = l[0] * ur[0][j * W];
