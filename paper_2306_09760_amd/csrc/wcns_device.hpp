@@ -98,10 +98,13 @@ __device__ __forceinline__ double rcp1(double x) {
 
 // sqrt(x) for x = 0 or 2^-760 <= x < inf (densities, pressures, sound speeds
 // squared): v_rsq_f64 seed, one Goldschmidt step for sqrt and 1/(2 sqrt),
-// two Newton corrections of the root (about 1 ulp); NaN for x < 0.  Without
-// the rescaling that a full-range square root needs for tiny arguments.
+// two Newton corrections of the root (about 1 ulp); NaN for x < -2^-1000.
+// Without the rescaling that a full-range square root needs for tiny
+// arguments.  The seed is taken at x + 2^-1000, which is x itself from
+// 2^-760 up and keeps x = 0 off the seed's pole: there every step below
+// gives g = 0 exactly, with no select.
 __device__ __forceinline__ double sqrt_pos(double x) {
-  const double y = __builtin_amdgcn_rsq(x);
+  const double y = __builtin_amdgcn_rsq(x + 0x1p-1000);
   double g = x * y, h = 0.5 * y;
   const double r = __builtin_fma(-h, g, 0.5);
   g = __builtin_fma(g, r, g);
@@ -110,7 +113,7 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   g = __builtin_fma(d, h, g);
   d = __builtin_fma(-g, g, x);
   g = __builtin_fma(d, h, g);
-  return x == 0.0 ? 0.0 : g;
+  return g;
 }
 
 // e^z for |z| <= 708 (Cody-Waite reduction z = n ln2 + r, |r| <= ln2/2, then
@@ -736,7 +739,7 @@ __device__ __forceinline__ void llf_flux(const double* UL, const double* UR, dou
   const double cR = sqrt_pos(gamma * R.p * R.ir);
   const double lamL = __builtin_fabs(L.vel[DIR]) + cL;
   const double lamR = __builtin_fabs(R.vel[DIR]) + cR;
-  const double alpha = (lamL >= lamR) ? lamL : lamR;
+  const double alpha = __builtin_fmax(lamL, lamR);  // (the larger; a NaN only if both are)
   FL[0] = UL[1 + DIR];
   FR[0] = UR[1 + DIR];
 #pragma unroll

@@ -235,8 +235,9 @@ __device__ __forceinline__ void emit(const A& a, int64_t gidx, int64_t vstride,
       double r = res[v];
       if (hr) r += rin[v];
       double s = __builtin_fma(crdt, r, a.cb * Un[v]);
-      if (h0) s = __builtin_fma(a.ca, u0[v], s);
-      y[v] = s;
+      // (with ca = 0, u0 is 0 and the term adds +0: no select; an exact
+      // zero result then comes out as +0)
+      y[v] = __builtin_fma(a.ca, u0[v], s);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = y[v];
@@ -253,9 +254,10 @@ __device__ __forceinline__ void emit(const A& a, int64_t gidx, int64_t vstride,
     for (int v = 0; v < NV; ++v) {
       double r = res[v];
       if (hr) r += rin[v];
-      double s = a.cb * __builtin_fma(dt, r, Un[v]);
-      if (h0) s = __builtin_fma(a.ca, u0[v], s);
-      y[v] = s;
+      const double s = a.cb * __builtin_fma(dt, r, Un[v]);
+      // (with ca = 0, u0 is 0 and the term adds +0: no select; an exact
+      // zero result then comes out as +0)
+      y[v] = __builtin_fma(a.ca, u0[v], s);
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) a.out[v * vstride + gidx] = y[v];

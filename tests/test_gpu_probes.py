@@ -106,3 +106,5 @@ def test_square_root_within_one_ulp(L, rng):
     y = _math(L, "sqrt", x)
     assert y[x.size - 4] == 0.0 and y[x.size - 3] == 1.0 and y[x.size - 2] == 2.0
     assert float(_ulps(y, np.sqrt(x.astype(np.longdouble))).max()) <= 1.0
+    # a negative argument (a non-physical state) gives NaN, not a number
+    assert np.isnan(_math(L, "sqrt", np.array([-1.0, -1e-300]))).all()
