@@ -1,5 +1,7 @@
-// Device helpers shared by the sweep kernels: boundary index map, status
-// flag and the per-node epilogue (R, R+= or the fused SSP-RK3 stage combine).
+// Device helpers shared by the sweep kernels: boundary index map, tile and
+// slot maps of packed lines, LDS row addresses and the stencil projection,
+// status flag and the per-node epilogue (R, R+= or the fused SSP-RK3 stage
+// combine).
 #pragma once
 
 #include <hip/hip_runtime.h>
